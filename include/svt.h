@@ -1,0 +1,199 @@
+/*
+ * svt.h -- C ABI of libsvt.so, the MI355X (gfx950) SVT linearized track fit.
+ *
+ * The operation (arXiv:1311.0380, Sec. 2 and Sec. 2.1): for every event and
+ * every road of the event, enumerate every combination of one hit per
+ * silicon layer, evaluate the per-sector linearized fit
+ *     p_i = f_i . x + q_i            (Sec. 2, the fit equation)
+ * for six rows -- rows 0..2 the track words (d0, phi, curvature), rows 3..5
+ * the chi2 constraint components -- form chi2 = y3^2 + y4^2 + y5^2 with
+ * integer additions and multiplications (Sec. 2), apply the chi2 cut and
+ * keep the best passing combination of each road.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - fit input of a combination: x = (h0[i0], h1[i1], h2[i2], h3[i3], xft0, xft1),
+ *     every word in [0, 4096);
+ *   - combination index k = ((i0*n1 + i1)*n2 + i2)*n3 + i3 (layer 0 most
+ *     significant: the order of the nested loops of Sec. 2.1);
+ *   - arithmetic is exact: y_k in int32 (guaranteed by the constant bound
+ *     checked at load), chi2 in uint64, no shift and no rounding;
+ *   - a combination passes when chi2 <= cut; the best is the passing
+ *     combination with the smallest chi2, ties to the smallest k.
+ *
+ * All functions return svt_status (SVT_OK = 0, negative = error), never throw,
+ * and may be called from several threads as long as calls on one context are
+ * serialized by the caller.
+ */
+#ifndef SVT_H
+#define SVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t svt_status;
+typedef int64_t svt_ticket;
+typedef struct svt_ctx svt_ctx;
+typedef struct svt_plan svt_plan;
+
+enum {
+    SVT_OK = 0,
+    SVT_E_INVAL = -1,   /* malformed call: NULL pointer, negative count, bad kind  */
+    SVT_E_RANGE = -2,   /* malformed data: see svt_summary.err_road / err_event    */
+    SVT_E_NOMEM = -3,   /* the request exceeds the context's device-memory budget  */
+    SVT_E_STATE = -4,   /* wrong state: no constants loaded, tickets in flight ... */
+    SVT_E_AGAIN = -5,   /* not finished yet (poll) / no free ticket slot          */
+    SVT_E_DEVICE = -6   /* a HIP runtime error; svt_last_error() has its text      */
+};
+
+/* Where a buffer lives. */
+enum {
+    SVT_MEM_PAGEABLE = 0,  /* ordinary host memory: copied through the DMA engine     */
+    SVT_MEM_PINNED = 1,    /* page-locked host memory (hipHostMalloc): async DMA copy  */
+    SVT_MEM_MAPPED = 2,    /* page-locked host memory mapped into the GPU address
+                              space: kernels read / write it in place (zero copy)      */
+    SVT_MEM_DEVICE = 3     /* device memory (hipMalloc, torch CUDA tensors)            */
+};
+
+/*
+ * One batch of events (Sec. 2: events contain roads; a road holds the hits of
+ * each layer and selects a sector constant set).  CSR layout:
+ *   road_offsets [n_events+1] int32   roads of event e: [road_offsets[e], road_offsets[e+1]);
+ *                                     road_offsets[0] = 0, nondecreasing, last = n_roads
+ *   sector       [n_roads]    uint8   constant set of the road, < n_sectors
+ *   nhits        [n_roads*4]  uint8   hits in layers 0..3, each 0..16 (0 = no combination)
+ *   hit_offsets  [n_roads+1]  int32   hits of road r: [hit_offsets[r], hit_offsets[r+1]),
+ *                                     difference = sum of nhits; first 0, last = n_hits
+ *   hits         [n_hits]     int16   hit words, layer-major inside a road, in [0, 4096)
+ *   xft          [n_roads*2]  int16   the road's two XFT words (curvature, phi), in [0, 4096)
+ * All pointers share mem_kind.  nhits and xft must be 4-byte aligned.
+ */
+typedef struct {
+    int32_t n_events, n_roads, n_hits, mem_kind;
+    const int32_t *road_offsets;
+    const uint8_t *sector;
+    const uint8_t *nhits;
+    const int32_t *hit_offsets;
+    const int16_t *hits;
+    const int16_t *xft;
+} svt_event_batch;
+
+/*
+ * Per-road and per-event results (Sec. 2: d0, phi, p_T word and chi2 of the
+ * fitted track).  Sizes are those of the batch they answer.
+ *   ncomb     [n_roads]   int32   n0*n1*n2*n3
+ *   npass     [n_roads]   int32   combinations with chi2 <= cut
+ *   best      [n_roads]   int32   k of the best passing combination, -1 if none
+ *   chi2      [n_roads]   uint64  its chi2, UINT64_MAX if none
+ *   params    [n_roads*3] int32   its fit rows 0..2, 0 if none
+ *   hit_index [n_roads*4] uint8   its (i0, i1, i2, i3), 0xFF if none (4-byte aligned)
+ *   ntracks   [n_events]  int32   roads of the event with a best combination
+ *   comb_offsets [n_roads+1] int64, may be NULL: exclusive prefix sum of ncomb
+ * All pointers share mem_kind.  On any error status the contents are unspecified.
+ */
+typedef struct {
+    int32_t *ncomb;
+    int32_t *npass;
+    int32_t *best;
+    uint64_t *chi2;
+    int32_t *params;
+    uint8_t *hit_index;
+    int32_t *ntracks;
+    int64_t *comb_offsets;
+    int32_t mem_kind;
+    int32_t pad_;
+} svt_results;
+
+typedef struct {
+    int64_t total_comb;     /* sum of ncomb                                       */
+    int64_t total_pass;     /* sum of npass                                       */
+    int32_t total_tracks;   /* sum of ntracks                                     */
+    int32_t err_road;       /* lowest malformed road, -1 if none                  */
+    int32_t err_event;      /* lowest malformed event, -1 if none                 */
+    int32_t status;         /* status of the request (same as svt_result returns) */
+    int64_t device_ns;      /* device time between the request's first and last
+                               command (copies included)                          */
+} svt_summary;
+
+/* Launch shape of the fit kernel; 0 in any field keeps the current value. */
+typedef struct {
+    int32_t events_per_chunk;  /* events per work item (1..256); 0 = automatic    */
+    int32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu (1..16)   */
+    int32_t schedule;          /* 1 = static round robin, 2 = dynamic work counter */
+    int32_t reserved;
+} svt_tuning;
+
+/*
+ * Context: one device, its resident constants, a device-memory budget for
+ * staging buffers and scratch, a stream and a ring of ticket slots.
+ * device: HIP device ordinal.  hbm_budget_bytes: upper bound on the device
+ * memory the context may allocate (0 = no bound).  *out receives the context.
+ * Errors: SVT_E_INVAL (out NULL, bad device), SVT_E_DEVICE, SVT_E_NOMEM.
+ */
+svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes);
+/* Waits for all requests of the context, then frees everything it owns. */
+svt_status svt_destroy(svt_ctx *ctx);
+
+/*
+ * Per-sector constant sets f_i, q_i of the linearized fit (Sec. 2) and the
+ * chi2 cut.  coef [n_sectors][6][6] int32 row-major (coef[s][k][j] multiplies
+ * input j in row k); offset [n_sectors][6] int32; host memory, copied -- the
+ * caller may free it on return.  n_sectors in 1..256; chi2_cut < 2^48.
+ * Every row must satisfy sum_j |coef[s][k][j]|*4095 + |offset[s][k]| <= 2^31-1
+ * (then every fit row is exact in int32).  Errors: SVT_E_INVAL (NULL,
+ * n_sectors out of range), SVT_E_RANGE (bound or cut violated), SVT_E_STATE
+ * (requests in flight), SVT_E_DEVICE.
+ */
+svt_status svt_load_constants(svt_ctx *ctx, int32_t n_sectors, const int32_t *coef,
+                              const int32_t *offset, uint64_t chi2_cut);
+
+/*
+ * Fit every road of a batch (asynchronous).  Copies host inputs to device
+ * staging (PAGEABLE, PINNED), or reads them in place (MAPPED, DEVICE), runs
+ * the fit, and copies results back when they are host memory.  hip_stream is
+ * a hipStream_t (NULL = the context's stream).  The caller keeps every
+ * buffer alive and unmodified until svt_result() has returned something other
+ * than SVT_E_AGAIN for *ticket.  Errors returned here: SVT_E_INVAL,
+ * SVT_E_STATE (no constants), SVT_E_NOMEM (staging over budget), SVT_E_AGAIN
+ * (all ticket slots in flight), SVT_E_DEVICE.  Data errors (SVT_E_RANGE) are
+ * found on the device and reported by svt_result().
+ */
+svt_status svt_fit_events(svt_ctx *ctx, const svt_event_batch *batch, const svt_results *res,
+                          void *hip_stream, svt_ticket *ticket);
+
+/*
+ * Completion of a request.  wait_us: -1 blocks, 0 polls, > 0 waits at most
+ * that long.  Returns SVT_E_AGAIN while running; otherwise the request's
+ * status (SVT_OK, SVT_E_RANGE with err_road / err_event set, SVT_E_DEVICE),
+ * fills *out (may be NULL) and releases the ticket.  Unknown or released
+ * tickets: SVT_E_INVAL.
+ */
+svt_status svt_result(svt_ctx *ctx, svt_ticket ticket, int32_t wait_us, svt_summary *out);
+
+/* Static text for a status; svt_last_error() is the last HIP error text of
+ * the calling thread (empty if none). */
+const char *svt_status_string(svt_status status);
+const char *svt_last_error(void);
+
+/* Launch shape used by later requests (affects speed only, never results). */
+svt_status svt_set_tuning(svt_ctx *ctx, const svt_tuning *tuning);
+svt_status svt_get_tuning(svt_ctx *ctx, svt_tuning *tuning);
+
+/* Device facts used for reporting: compute units, clock (kHz), HBM bytes. */
+typedef struct {
+    int32_t compute_units;
+    int32_t clock_khz;
+    int64_t hbm_bytes;
+    int64_t budget_bytes;
+    int64_t used_bytes;
+    char arch[32];
+} svt_device_info;
+svt_status svt_get_device_info(svt_ctx *ctx, svt_device_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVT_H */

@@ -1,0 +1,655 @@
+// Fused SVT fit kernel for gfx950 (arXiv:1311.0380, Sec. 2 / Sec. 2.1).
+//
+// One persistent grid.  Work item = a chunk of `events_per_chunk` consecutive
+// events, so every event (and its track count) belongs to exactly one block.
+// A chunk's roads are processed in sub-chunks of at most kSubRoads roads whose
+// hits (kHitCap) and (i0, i1) rows (kRowCap) fit in LDS:
+//
+//   A  one thread per road: load + validate the road, prefix sums give each
+//      road its slot in the LDS hit table and row list; the road's rows are
+//      binned by (n2, n3) so that a wavefront's rows share their inner trip
+//      counts; the hits are staged in LDS as fp64 (coalesced, flattened);
+//      the constraint rows' constant part b + A[:,4] x4 + A[:,5] x5 is formed.
+//   B  one thread per row (i0, i1): z = base + A[:,0] h0 + A[:,1] h1, then for
+//      every (i2, i3) the three constraint rows y3..y5 and chi2 in fp64.  Every
+//      value is an integer below 2^53 whenever chi2 <= cut < 2^48, so the pass
+//      test, the pass count and the minimum are exact; larger chi2 round to
+//      values that still exceed the cut.  The row's best (chi2, i2, i3) is
+//      merged into the road with one LDS atomicMin on the key
+//      chi2 << 16 | i0 << 12 | i1 << 8 | i2 << 4 | i3, whose order is the
+//      order of (chi2, combination index k) because each i_l < n_l <= 16.
+//   C  one thread per road: decode the winner, recompute its parameter rows
+//      0..2 exactly in int32, write the road's results, count tracks per event.
+//
+// The last block to finish reduces the per-block partial sums into the request
+// summary and resets the request's counters.
+#include "svt_internal.h"
+
+namespace svt {
+namespace {
+
+constexpr int kBins = 17 * 17;   // (n2, n3) in 0..16 x 0..16
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t t = __shfl_up(x, off, 64);
+        if (lane >= off) x += t;
+    }
+    return x;
+}
+
+// Block-wide exclusive scan of a value holding two packed 32-bit counters.
+__device__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_warp, uint64_t &total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t incl = wave_incl_scan(v, lane);
+    if (lane == 63) s_warp[wid] = incl;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        uint64_t s = s_warp[w];
+        before += (w < wid) ? s : 0;
+        tot += s;
+    }
+    total = tot;
+    __syncthreads();
+    return before + incl - v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        uint32_t t = __shfl_xor(v, off, 64);
+        v = v > t ? v : t;
+    }
+    return v;
+}
+
+struct RowState {
+    double z3, z4, z5;   // constraint rows with layers 0, 1 and the XFT words
+    double a3, a4, a5;   // column of layer 2
+    double c3, c4, c5;   // column of layer 3
+    double bc;           // best chi2 of the row so far (starts at cut + 1)
+    uint32_t bidx;       // (i2 << 4) | i3 of the best, ~0 if none
+    uint32_t np;         // passing combinations
+};
+
+// Inner loops with trip counts shared by the whole wavefront.
+template <int N3>
+__device__ __forceinline__ void row_loop_uniform(RowState &st, const double *s_hit, uint32_t p2,
+                                                 uint32_t n2, double cut)
+{
+    const uint32_t p3 = p2 + n2;
+    for (uint32_t i2 = 0; i2 < n2; ++i2) {
+        const double h2 = s_hit[p2 + i2];
+        const double q3 = fma(st.a3, h2, st.z3);
+        const double q4 = fma(st.a4, h2, st.z4);
+        const double q5 = fma(st.a5, h2, st.z5);
+#pragma unroll
+        for (int i3 = 0; i3 < N3; ++i3) {
+            const double h3 = s_hit[p3 + i3];
+            const double y3 = fma(st.c3, h3, q3);
+            const double y4 = fma(st.c4, h3, q4);
+            const double y5 = fma(st.c5, h3, q5);
+            const double c = fma(y5, y5, fma(y4, y4, y3 * y3));
+            st.np += (c <= cut) ? 1u : 0u;
+            if (c < st.bc) {
+                st.bc = c;
+                st.bidx = (i2 << 4) | (uint32_t)i3;
+            }
+        }
+    }
+}
+
+// Inner loops for a wavefront whose rows have different (n2, n3).
+__device__ __forceinline__ void row_loop_mixed(RowState &st, const double *s_hit, uint32_t p2,
+                                               uint32_t n2, uint32_t n3, uint32_t n2w,
+                                               uint32_t n3w, double cut)
+{
+    const uint32_t p3 = p2 + n2;
+    for (uint32_t i2 = 0; i2 < n2w; ++i2) {
+        if (i2 < n2) {
+            const double h2 = s_hit[p2 + i2];
+            const double q3 = fma(st.a3, h2, st.z3);
+            const double q4 = fma(st.a4, h2, st.z4);
+            const double q5 = fma(st.a5, h2, st.z5);
+            for (uint32_t i3 = 0; i3 < n3w; ++i3) {
+                if (i3 < n3) {
+                    const double h3 = s_hit[p3 + i3];
+                    const double y3 = fma(st.c3, h3, q3);
+                    const double y4 = fma(st.c4, h3, q4);
+                    const double y5 = fma(st.c5, h3, q5);
+                    const double c = fma(y5, y5, fma(y4, y4, y3 * y3));
+                    st.np += (c <= cut) ? 1u : 0u;
+                    if (c < st.bc) {
+                        st.bc = c;
+                        st.bidx = (i2 << 4) | i3;
+                    }
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+struct Acc {
+    uint64_t comb = 0, pass = 0;
+    uint32_t tracks = 0;
+    uint32_t err_road = 0xFFFFFFFFu, err_event = 0xFFFFFFFFu;
+};
+
+struct Shared {
+    double hit[kHitCap];
+    uint64_t row[kRowCap];
+    double base[3][kSubRoads];
+    unsigned long long key[kSubRoads];
+    uint32_t np[kSubRoads];
+    uint32_t hb[kSubRoads];
+    uint32_t bin[kBins];
+    int32_t evro[kMaxEventsPerChunk + 1];
+    uint32_t evcnt[kMaxEventsPerChunk];
+    uint64_t warp[kWaves];
+    uint8_t sec[kSubRoads];
+    int32_t misc[4];
+};
+
+// Process the roads [s, rb) of the current chunk starting at road s; returns
+// how many roads were fitted (at least one when s < rb).
+__device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, const int32_t *s_ci,
+                           int32_t s, int32_t rb, int32_t n_roads, int32_t n_hits,
+                           int32_t n_sectors, int32_t ne, double cut, Acc &acc)
+{
+    const int tid = threadIdx.x;
+    const int32_t r = s + tid;
+    const bool inr = r < rb;
+
+    uint32_t sec = 0, nh4 = 0, x2 = 0;
+    int32_t h0 = 0, h1 = 0;
+    if (inr) {
+        sec = a.sector[r];
+        nh4 = a.nhits4[r];
+        h0 = a.hit_offsets[r];
+        h1 = a.hit_offsets[r + 1];
+        x2 = a.xft2[r];
+    }
+    const uint32_t n0 = nh4 & 255u, n1 = (nh4 >> 8) & 255u, n2 = (nh4 >> 16) & 255u,
+                   n3 = nh4 >> 24;
+    const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
+    const uint32_t sum = n0 + n1 + n2 + n3;
+    bool ok = inr && sec < (uint32_t)n_sectors && n0 <= 16 && n1 <= 16 && n2 <= 16 && n3 <= 16;
+    ok = ok && h0 >= 0 && h1 <= n_hits && (int64_t)h1 - (int64_t)h0 == (int64_t)sum;
+    ok = ok && (r != 0 || h0 == 0) && (r != n_roads - 1 || h1 == n_hits);
+    ok = ok && xa >= 0 && xa < 4096 && xb >= 0 && xb < 4096;
+    if (inr && !ok) acc.err_road = min(acc.err_road, (uint32_t)r);
+
+    const uint32_t nh = ok ? sum : 0u;
+    const uint32_t rows = (ok && n2 * n3 > 0) ? n0 * n1 : 0u;
+    uint64_t total;
+    const uint64_t ex = block_excl_scan((uint64_t)nh | ((uint64_t)rows << 32), S.warp, total);
+    const uint32_t hb = (uint32_t)ex, rbase = (uint32_t)(ex >> 32);
+    const bool fits = inr && hb + nh <= (uint32_t)kHitCap && rbase + rows <= (uint32_t)kRowCap;
+    const int L = __syncthreads_count(fits);
+    const bool active = tid < L;   // fits is a prefix of the block
+
+    if (tid == L - 1) {
+        S.misc[1] = (int32_t)(hb + nh);           // hits of the sub-chunk
+        S.misc[3] = (int32_t)(rbase + rows);      // rows of the sub-chunk
+    }
+    if (tid == 0) S.misc[2] = clampi(h0, 0, n_hits);
+    if (active) {
+        S.hb[tid] = hb;
+        S.sec[tid] = (uint8_t)(ok ? sec : 0u);
+        S.key[tid] = ~0ull;
+        S.np[tid] = 0;
+    }
+    for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;
+    __syncthreads();
+
+    const int32_t T = S.misc[1], hs = S.misc[2], total_rows = S.misc[3];
+    const uint32_t bkey = n2 * 17u + n3;
+    uint32_t boff = 0;
+    if (active && rows) boff = atomicAdd(&S.bin[bkey], rows);
+
+    // stage the sub-chunk's hits (contiguous in the batch), check their range
+    for (int t = tid; t < T; t += kBlock) {
+        const int32_t g = hs + t;
+        const int32_t h = g < n_hits ? (int32_t)a.hits[g] : 0;
+        S.hit[t] = (double)h;
+        if (h < 0 || h >= 4096) {
+            int lo = 0, hi = L;     // last road with hb <= t
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if ((int32_t)S.hb[mid] <= t) lo = mid; else hi = mid;
+            }
+            acc.err_road = min(acc.err_road, (uint32_t)(s + lo));
+        }
+    }
+    // constant part of the constraint rows: b + A[:,4] x4 + A[:,5] x5
+    if (active && ok) {
+        const double *cs = s_cd + sec * kCstDoubles;
+        const double x4 = (double)xa, x5 = (double)xb;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            S.base[k][tid] = fma(cs[15 + k], x5, fma(cs[12 + k], x4, cs[18 + k]));
+    }
+    __syncthreads();
+
+    // bin starts: exclusive scan of the 289 bins by wave 0
+    if (tid < 64) {
+        uint32_t v[5], loc = 0;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int b = tid * 5 + q;
+            v[q] = b < kBins ? S.bin[b] : 0u;
+            loc += v[q];
+        }
+        const uint64_t incl = wave_incl_scan(loc, tid);
+        uint32_t run = (uint32_t)incl - loc;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int b = tid * 5 + q;
+            if (b < kBins) S.bin[b] = run;
+            run += v[q];
+        }
+    }
+    __syncthreads();
+
+    // rows of the road, in (i0, i1) order, at its place in the binned list
+    if (active && rows) {
+        uint32_t w = S.bin[bkey] + boff;
+        const uint64_t common = ((uint64_t)(hb + n0 + n1) << 24) | ((uint64_t)n2 << 36) |
+                                ((uint64_t)n3 << 41) | ((uint64_t)tid << 46);
+        for (uint32_t i0 = 0; i0 < n0; ++i0)
+            for (uint32_t i1 = 0; i1 < n1; ++i1, ++w)
+                S.row[w] = common | (uint64_t)(hb + i0) | ((uint64_t)(hb + n0 + i1) << 12) |
+                           ((uint64_t)i0 << 54) | ((uint64_t)i1 << 58);
+    }
+    __syncthreads();
+
+    // B: every combination of every row
+    for (int idx0 = 0; idx0 < total_rows; idx0 += kBlock) {
+        if (idx0 + (tid & ~63) >= total_rows) continue;   // whole wavefront idle
+        const int idx = idx0 + tid;
+        const bool act = idx < total_rows;
+        const uint64_t d = S.row[act ? idx : total_rows - 1];
+        const uint32_t p0 = (uint32_t)d & 0xFFFu, p1 = (uint32_t)(d >> 12) & 0xFFFu,
+                       p2 = (uint32_t)(d >> 24) & 0xFFFu;
+        const uint32_t rn2 = (uint32_t)(d >> 36) & 31u, rn3 = (uint32_t)(d >> 41) & 31u;
+        const uint32_t j = (uint32_t)(d >> 46) & 255u;
+        const uint32_t i0 = (uint32_t)(d >> 54) & 15u, i1 = (uint32_t)(d >> 58) & 15u;
+        const double *cs = s_cd + (uint32_t)S.sec[j] * kCstDoubles;
+        const double h0v = S.hit[p0], h1v = S.hit[p1];
+        RowState st;
+        st.z3 = fma(cs[3], h1v, fma(cs[0], h0v, S.base[0][j]));
+        st.z4 = fma(cs[4], h1v, fma(cs[1], h0v, S.base[1][j]));
+        st.z5 = fma(cs[5], h1v, fma(cs[2], h0v, S.base[2][j]));
+        st.a3 = cs[6];
+        st.a4 = cs[7];
+        st.a5 = cs[8];
+        st.c3 = cs[9];
+        st.c4 = cs[10];
+        st.c5 = cs[11];
+        st.bc = cut + 1.0;
+        st.bidx = 0xFFFFFFFFu;
+        st.np = 0;
+        const uint32_t nn = (rn2 << 8) | rn3;
+        const uint32_t first = __builtin_amdgcn_readfirstlane(nn);
+        if (__all(nn == first)) {
+            const uint32_t un2 = first >> 8;
+            switch (first & 31u) {
+            case 1: row_loop_uniform<1>(st, S.hit, p2, un2, cut); break;
+            case 2: row_loop_uniform<2>(st, S.hit, p2, un2, cut); break;
+            case 3: row_loop_uniform<3>(st, S.hit, p2, un2, cut); break;
+            case 4: row_loop_uniform<4>(st, S.hit, p2, un2, cut); break;
+            case 5: row_loop_uniform<5>(st, S.hit, p2, un2, cut); break;
+            case 6: row_loop_uniform<6>(st, S.hit, p2, un2, cut); break;
+            case 7: row_loop_uniform<7>(st, S.hit, p2, un2, cut); break;
+            case 8: row_loop_uniform<8>(st, S.hit, p2, un2, cut); break;
+            case 9: row_loop_uniform<9>(st, S.hit, p2, un2, cut); break;
+            case 10: row_loop_uniform<10>(st, S.hit, p2, un2, cut); break;
+            case 11: row_loop_uniform<11>(st, S.hit, p2, un2, cut); break;
+            case 12: row_loop_uniform<12>(st, S.hit, p2, un2, cut); break;
+            case 13: row_loop_uniform<13>(st, S.hit, p2, un2, cut); break;
+            case 14: row_loop_uniform<14>(st, S.hit, p2, un2, cut); break;
+            case 15: row_loop_uniform<15>(st, S.hit, p2, un2, cut); break;
+            case 16: row_loop_uniform<16>(st, S.hit, p2, un2, cut); break;
+            default: break;
+            }
+        } else {
+            const uint32_t n2w = wave_max_u32(rn2), n3w = wave_max_u32(rn3);
+            row_loop_mixed(st, S.hit, p2, rn2, rn3, __builtin_amdgcn_readfirstlane(n2w),
+                           __builtin_amdgcn_readfirstlane(n3w), cut);
+        }
+        if (act) {
+            if (st.bidx != 0xFFFFFFFFu) {
+                const unsigned long long key = ((unsigned long long)st.bc << 16) |
+                                               (i0 << 12) | (i1 << 8) | st.bidx;
+                atomicMin(&S.key[j], key);
+            }
+            if (st.np) atomicAdd(&S.np[j], st.np);
+        }
+    }
+    __syncthreads();
+
+    // C: results of each road
+    if (active) {
+        const unsigned long long key = S.key[tid];
+        const uint32_t np = S.np[tid];
+        const bool found = ok && key != ~0ull;
+        int32_t bk = -1;
+        uint64_t c2 = ~0ull;
+        int32_t p[3] = {0, 0, 0};
+        uint32_t hi4 = 0xFFFFFFFFu;
+        if (found) {
+            const uint32_t i0 = (uint32_t)(key >> 12) & 15u, i1 = (uint32_t)(key >> 8) & 15u,
+                           i2 = (uint32_t)(key >> 4) & 15u, i3 = (uint32_t)key & 15u;
+            c2 = key >> 16;
+            bk = (int32_t)(((i0 * n1 + i1) * n2 + i2) * n3 + i3);
+            hi4 = i0 | (i1 << 8) | (i2 << 16) | (i3 << 24);
+            const uint32_t x[6] = {(uint32_t)(int32_t)S.hit[hb + i0],
+                                   (uint32_t)(int32_t)S.hit[hb + n0 + i1],
+                                   (uint32_t)(int32_t)S.hit[hb + n0 + n1 + i2],
+                                   (uint32_t)(int32_t)S.hit[hb + n0 + n1 + n2 + i3],
+                                   (uint32_t)xa, (uint32_t)xb};
+            const int32_t *ci = s_ci + sec * kCstInts;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                uint32_t v = (uint32_t)ci[18 + k];   // exact in int32 by the load-time bound
+#pragma unroll
+                for (int col = 0; col < 6; ++col) v += (uint32_t)ci[col * 3 + k] * x[col];
+                p[k] = (int32_t)v;
+            }
+        }
+        a.ncomb[r] = ok ? (int32_t)(n0 * n1 * n2 * n3) : 0;
+        a.npass[r] = ok ? (int32_t)np : 0;
+        a.best[r] = bk;
+        a.chi2[r] = c2;
+        a.params[3 * (int64_t)r + 0] = p[0];
+        a.params[3 * (int64_t)r + 1] = p[1];
+        a.params[3 * (int64_t)r + 2] = p[2];
+        a.hit_index4[r] = hi4;
+        if (found) {
+            int lo = 0, hi = ne;   // events [lo, hi): largest e with evro[e] <= r
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (S.evro[mid] <= r) lo = mid; else hi = mid;
+            }
+            atomicAdd(&S.evcnt[lo], 1u);
+        }
+        if (ok) {
+            acc.comb += n0 * n1 * n2 * n3;
+            acc.pass += np;
+            acc.tracks += found ? 1u : 0u;
+        }
+    }
+    __syncthreads();
+    return L;
+}
+
+__global__ void __launch_bounds__(kBlock) fit_kernel(FitArgs a)
+{
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    __shared__ Shared S;
+    const int tid = threadIdx.x;
+
+    int32_t n_events = a.n_events, n_roads = a.n_roads, n_hits = a.n_hits;
+    if (a.sizes != nullptr) {
+        n_events = a.sizes->n_events;
+        n_roads = a.sizes->n_roads;
+        n_hits = a.sizes->n_hits;
+    }
+    const int32_t n_sectors = a.n_sectors;
+    double *s_cd = reinterpret_cast<double *>(s_dyn);
+    int32_t *s_ci = reinterpret_cast<int32_t *>(s_dyn + (size_t)n_sectors * kCstDoubles * 8);
+
+    // sector constants -> LDS: constraint rows as fp64, parameter rows as int32
+    for (int i = tid; i < n_sectors * 6; i += kBlock) {
+        const int sct = i / 6, col = i - sct * 6;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_cd[sct * kCstDoubles + col * 3 + k] = (double)a.coef[(sct * 6 + 3 + k) * 6 + col];
+            s_ci[sct * kCstInts + col * 3 + k] = a.coef[(sct * 6 + k) * 6 + col];
+        }
+    }
+    for (int sct = tid; sct < n_sectors; sct += kBlock) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_cd[sct * kCstDoubles + 18 + k] = (double)a.offset[sct * 6 + 3 + k];
+            s_ci[sct * kCstInts + 18 + k] = a.offset[sct * 6 + k];
+        }
+    }
+    __syncthreads();
+
+    Acc acc;
+    const double cut = a.cut_d;
+    const int32_t E = a.events_per_chunk;
+    const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
+
+    int32_t c;
+    if (a.schedule == 2) {
+        if (tid == 0) S.misc[0] = (int32_t)atomicAdd(a.work, 1u);
+        __syncthreads();
+        c = S.misc[0];
+        __syncthreads();
+    } else {
+        c = blockIdx.x;
+    }
+    while (c < n_chunks) {
+        const int32_t e0 = c * E;
+        const int32_t ne = min(E, n_events - e0);
+        for (int i = tid; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
+        for (int i = tid; i < ne; i += kBlock) S.evcnt[i] = 0;
+        __syncthreads();
+        for (int i = tid; i < ne; i += kBlock) {
+            const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
+            const bool bad = lo < 0 || hi < lo || hi > n_roads || (e == 0 && lo != 0) ||
+                             (e == n_events - 1 && hi != n_roads);
+            if (bad) acc.err_event = min(acc.err_event, (uint32_t)e);
+        }
+        const int32_t ra = clampi(S.evro[0], 0, n_roads);
+        const int32_t rb = clampi(S.evro[ne], ra, n_roads);
+        for (int32_t s = ra; s < rb;)
+            s += process_sub(a, S, s_cd, s_ci, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc);
+        __syncthreads();
+        for (int i = tid; i < ne; i += kBlock) a.ntracks[e0 + i] = (int32_t)S.evcnt[i];
+        __syncthreads();
+        if (a.schedule == 2) {
+            if (tid == 0) S.misc[0] = (int32_t)atomicAdd(a.work, 1u);
+            __syncthreads();
+            c = S.misc[0];
+            __syncthreads();
+        } else {
+            c += gridDim.x;
+        }
+    }
+
+    // block partials -> last block -> request summary
+    const int lane = tid & 63, wid = tid >> 6;
+    uint64_t comb = acc.comb, pass = acc.pass;
+    uint32_t trk = acc.tracks, er = acc.err_road, ee = acc.err_event;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        comb += __shfl_xor(comb, off, 64);
+        pass += __shfl_xor(pass, off, 64);
+        trk += __shfl_xor(trk, off, 64);
+        er = min(er, (uint32_t)__shfl_xor(er, off, 64));
+        ee = min(ee, (uint32_t)__shfl_xor(ee, off, 64));
+    }
+    __shared__ BlockPartial s_part[kWaves];
+    __shared__ int s_last;
+    if (lane == 0) s_part[wid] = BlockPartial{comb, pass, trk, er, ee, 0};
+    __syncthreads();
+    if (tid == 0) {
+        BlockPartial p = s_part[0];
+        for (int w = 1; w < kWaves; ++w) {
+            p.comb += s_part[w].comb;
+            p.pass += s_part[w].pass;
+            p.tracks += s_part[w].tracks;
+            p.err_road = min(p.err_road, s_part[w].err_road);
+            p.err_event = min(p.err_event, s_part[w].err_event);
+        }
+        a.partials[blockIdx.x] = p;
+        __threadfence();
+        const uint32_t prev = atomicAdd(a.done, 1u);
+        s_last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    comb = 0;
+    pass = 0;
+    trk = 0;
+    er = 0xFFFFFFFFu;
+    ee = 0xFFFFFFFFu;
+    for (uint32_t b = tid; b < gridDim.x; b += kBlock) {
+        const BlockPartial p = a.partials[b];
+        comb += p.comb;
+        pass += p.pass;
+        trk += p.tracks;
+        er = min(er, p.err_road);
+        ee = min(ee, p.err_event);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        comb += __shfl_xor(comb, off, 64);
+        pass += __shfl_xor(pass, off, 64);
+        trk += __shfl_xor(trk, off, 64);
+        er = min(er, (uint32_t)__shfl_xor(er, off, 64));
+        ee = min(ee, (uint32_t)__shfl_xor(ee, off, 64));
+    }
+    __syncthreads();
+    if (lane == 0) s_part[wid] = BlockPartial{comb, pass, trk, er, ee, 0};
+    __syncthreads();
+    if (tid == 0) {
+        BlockPartial p = s_part[0];
+        for (int w = 1; w < kWaves; ++w) {
+            p.comb += s_part[w].comb;
+            p.pass += s_part[w].pass;
+            p.tracks += s_part[w].tracks;
+            p.err_road = min(p.err_road, s_part[w].err_road);
+            p.err_event = min(p.err_event, s_part[w].err_event);
+        }
+        SummaryDev *out = a.summary;
+        out->total_comb = (int64_t)p.comb;
+        out->total_pass = (int64_t)p.pass;
+        out->total_tracks = (int32_t)p.tracks;
+        out->err_road = p.err_road == 0xFFFFFFFFu ? -1 : (int32_t)p.err_road;
+        out->err_event = p.err_event == 0xFFFFFFFFu ? -1 : (int32_t)p.err_event;
+        out->status = (p.err_road != 0xFFFFFFFFu || p.err_event != 0xFFFFFFFFu) ? -2 : 0;
+        *a.done = 0;
+        *a.work = 0;
+        __threadfence_system();
+        out->seq = a.seq;
+        __threadfence_system();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// comb_offsets: exclusive prefix sum of ncomb (int64), three small passes
+// ---------------------------------------------------------------------------
+constexpr int kScanTile = kBlock * 8;
+
+__global__ void __launch_bounds__(kBlock) scan_tiles(const int32_t *ncomb, int32_t n, int64_t *tile_sum)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+    for (int i = threadIdx.x; i < kScanTile; i += kBlock) {
+        const int64_t g = base + i;
+        if (g < n) s += ncomb[g];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    __shared__ int64_t w[kWaves];
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < kWaves; ++q) t += w[q];
+        tile_sum[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) scan_tile_sums(int64_t *tile_sum, int32_t n_tiles)
+{
+    __shared__ uint64_t warp[kWaves];
+    int64_t carry = 0;
+    for (int32_t b0 = 0; b0 < n_tiles; b0 += kBlock) {
+        const int32_t b = b0 + threadIdx.x;
+        const int64_t v = b < n_tiles ? tile_sum[b] : 0;
+        uint64_t tot;
+        const int64_t ex = (int64_t)block_excl_scan((uint64_t)v, warp, tot);
+        if (b < n_tiles) tile_sum[b] = carry + ex;
+        carry += (int64_t)tot;
+    }
+    if (threadIdx.x == 0) tile_sum[n_tiles] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) scan_apply(const int32_t *ncomb, int32_t n,
+                                                     const int64_t *tile_sum, int64_t *out)
+{
+    __shared__ uint64_t warp[kWaves];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t carry = tile_sum[blockIdx.x];
+    for (int i0 = 0; i0 < kScanTile; i0 += kBlock) {
+        const int64_t g = base + i0 + threadIdx.x;
+        const int64_t v = g < n ? ncomb[g] : 0;
+        uint64_t tot;
+        const int64_t ex = (int64_t)block_excl_scan((uint64_t)v, warp, tot);
+        if (g < n) out[g] = carry + ex;
+        carry += (int64_t)tot;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tile_sum[gridDim.x];
+}
+
+__global__ void zero_i64(int64_t *p)
+{
+    if (threadIdx.x == 0) p[0] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream)
+{
+    static bool attr_done = false;
+    if (!attr_done) {
+        const int max_dyn = 256 * kCstBytesPerSector;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), dyn_lds, stream, a);
+    return hipGetLastError();
+}
+
+size_t comb_offsets_scratch_bytes(int32_t n_roads)
+{
+    const int64_t tiles = ((int64_t)n_roads + kScanTile - 1) / kScanTile;
+    return (size_t)(tiles + 1) * sizeof(int64_t);
+}
+
+hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
+                               int64_t *scratch, hipStream_t stream)
+{
+    const int32_t tiles = (int32_t)(((int64_t)n_roads + kScanTile - 1) / kScanTile);
+    if (tiles == 0) {
+        hipLaunchKernelGGL(zero_i64, dim3(1), dim3(64), 0, stream, comb_offsets);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(scan_tiles, dim3(tiles), dim3(kBlock), 0, stream, ncomb, n_roads, scratch);
+    hipLaunchKernelGGL(scan_tile_sums, dim3(1), dim3(kBlock), 0, stream, scratch, tiles);
+    hipLaunchKernelGGL(scan_apply, dim3(tiles), dim3(kBlock), 0, stream, ncomb, n_roads, scratch,
+                       comb_offsets);
+    return hipGetLastError();
+}
+
+}  // namespace svt

@@ -1,0 +1,88 @@
+// Internal declarations shared by the host runtime and the kernels of libsvt.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace svt {
+
+// Launch geometry of the fused fit kernel.
+constexpr int kBlock = 256;        // threads per block (4 wave64)
+constexpr int kSubRoads = 256;     // roads per sub-chunk: one thread per road
+constexpr int kHitCap = 3072;      // hits staged in LDS per sub-chunk
+constexpr int kRowCap = 2048;      // (i0, i1) rows per sub-chunk
+constexpr int kMaxEventsPerChunk = 256;
+constexpr int kMaxBlocksPerCu = 16;
+// Per sector, in dynamic LDS: 24 doubles (constraint rows 3..5: 6 columns x 3
+// rows, then 3 offsets, 3 pad) followed by 24 int32 (parameter rows 0..2:
+// 6 columns x 3 rows, then 3 offsets, 3 pad).
+constexpr int kCstDoubles = 24;
+constexpr int kCstInts = 24;
+constexpr int kCstBytesPerSector = kCstDoubles * 8 + kCstInts * 4;
+
+// Sizes of a batch when they are read from device memory (graph replay).
+struct Sizes {
+    int32_t n_events, n_roads, n_hits, pad;
+};
+
+// Per-block partial sums of a request, reduced by the last block.
+struct BlockPartial {
+    uint64_t comb;
+    uint64_t pass;
+    uint32_t tracks;
+    uint32_t err_road;    // lowest bad road, 0xFFFFFFFF if none
+    uint32_t err_event;   // lowest bad event, 0xFFFFFFFF if none
+    uint32_t pad;
+};
+
+// Request summary written by the last block (host-mapped memory).
+struct SummaryDev {
+    int64_t total_comb;
+    int64_t total_pass;
+    int32_t total_tracks;
+    int32_t err_road;
+    int32_t err_event;
+    int32_t status;
+    uint32_t seq;          // request sequence number, written last
+    uint32_t pad;
+};
+
+struct FitArgs {
+    // batch (device-visible pointers)
+    const int32_t *road_offsets;
+    const uint8_t *sector;
+    const uint32_t *nhits4;     // 4 x uint8 per road
+    const int32_t *hit_offsets;
+    const int16_t *hits;
+    const uint32_t *xft2;       // 2 x int16 per road
+    int32_t n_events, n_roads, n_hits;
+    int32_t n_sectors;
+    const Sizes *sizes;         // non-NULL: sizes are read from here instead
+    // constants (device)
+    const int32_t *coef;        // [n_sectors][6][6]
+    const int32_t *offset;      // [n_sectors][6]
+    double cut_d;               // chi2 cut as a double (exact: < 2^48)
+    // results (device-visible pointers)
+    int32_t *ncomb;
+    int32_t *npass;
+    int32_t *best;
+    uint64_t *chi2;
+    int32_t *params;
+    uint32_t *hit_index4;       // 4 x uint8 per road
+    int32_t *ntracks;
+    // launch shape
+    int32_t events_per_chunk;
+    int32_t schedule;           // 1 static, 2 dynamic
+    // request bookkeeping (device)
+    BlockPartial *partials;     // [gridDim.x]
+    uint32_t *done;             // blocks finished; reset by the last block
+    uint32_t *work;             // dynamic work counter; reset by the last block
+    SummaryDev *summary;        // written by the last block
+    uint32_t seq;
+};
+
+hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream);
+hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
+                               int64_t *scratch, hipStream_t stream);
+size_t comb_offsets_scratch_bytes(int32_t n_roads);
+
+}  // namespace svt

@@ -1,0 +1,531 @@
+// Host runtime of libsvt: contexts, resident constants, staging, tickets.
+// Implements the C ABI declared in include/svt.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+
+#include "svt.h"
+#include "svt_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+svt_status hip_fail(hipError_t e, const char *what)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_last_error = buf;
+    return SVT_E_DEVICE;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+constexpr int kSlots = 64;
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+};
+
+struct Slot {
+    bool busy = false;
+    svt_ticket ticket = -1;
+    hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    svt::BlockPartial *partials = nullptr;   // device [max grid]
+    uint32_t *counters = nullptr;            // device [2]: done, work
+    svt::SummaryDev *summary = nullptr;      // host-mapped
+    DevBuf stage;                            // device staging for host inputs / results
+    DevBuf scan;                             // comb_offsets scratch
+    svt_status host_status = SVT_OK;
+};
+
+}  // namespace
+
+struct svt_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    int clock_khz = 0;
+    size_t hbm_bytes = 0;
+    char arch[32] = {0};
+    int max_grid = 0;
+    // constants
+    int32_t *coef = nullptr;
+    int32_t *offset = nullptr;
+    int32_t n_sectors = 0;
+    uint64_t cut = 0;
+    bool loaded = false;
+    // requests
+    Slot slots[kSlots];
+    svt_ticket next_ticket = 1;
+    svt_tuning tuning{0, 2, 1, 0};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+svt_status dev_alloc(svt_ctx *c, void **p, size_t bytes)
+{
+    if (c->budget && c->used + bytes > c->budget) return SVT_E_NOMEM;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return SVT_E_NOMEM;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    c->used += bytes;
+    return SVT_OK;
+}
+
+void dev_free(svt_ctx *c, void *p, size_t bytes)
+{
+    if (p) {
+        (void)hipFree(p);
+        c->used -= bytes;
+    }
+}
+
+svt_status ensure(svt_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (b.cap >= bytes) return SVT_OK;
+    size_t want = bytes + bytes / 4;
+    if (c->budget && c->used - b.cap + want > c->budget) want = bytes;
+    if (c->budget && c->used - b.cap + want > c->budget) return SVT_E_NOMEM;
+    dev_free(c, b.ptr, b.cap);
+    b.ptr = nullptr;
+    b.cap = 0;
+    void *p = nullptr;
+    svt_status st = dev_alloc(c, &p, want);
+    if (st != SVT_OK) return st;
+    b.ptr = p;
+    b.cap = want;
+    return SVT_OK;
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool kind_ok(int32_t k) { return k >= SVT_MEM_PAGEABLE && k <= SVT_MEM_DEVICE; }
+
+// Device-visible address of a caller buffer of the given kind.
+const void *device_view(const void *p, int32_t kind)
+{
+    if (p == nullptr || kind != SVT_MEM_MAPPED) return p;
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, const_cast<void *>(p), 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return p;   // on ROCm host pointers of pinned memory are valid device addresses
+    }
+    return d;
+}
+
+int auto_events_per_chunk(const svt_event_batch *b)
+{
+    if (b->n_events <= 0) return 1;
+    const double rpe = (double)b->n_roads / (double)b->n_events;
+    int e = rpe > 0 ? (int)(256.0 / rpe) : 256;
+    if (e < 1) e = 1;
+    if (e > svt::kMaxEventsPerChunk) e = svt::kMaxEventsPerChunk;
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *svt_status_string(svt_status s)
+{
+    switch (s) {
+    case SVT_OK: return "SVT_OK";
+    case SVT_E_INVAL: return "SVT_E_INVAL: malformed call";
+    case SVT_E_RANGE: return "SVT_E_RANGE: malformed data";
+    case SVT_E_NOMEM: return "SVT_E_NOMEM: over the device-memory budget";
+    case SVT_E_STATE: return "SVT_E_STATE: wrong state";
+    case SVT_E_AGAIN: return "SVT_E_AGAIN: not finished / no free slot";
+    case SVT_E_DEVICE: return "SVT_E_DEVICE: HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char *svt_last_error(void) { return g_last_error.c_str(); }
+
+svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes)
+{
+    if (out == nullptr) return SVT_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return SVT_E_INVAL;
+    DeviceGuard g(device);
+    svt_ctx *c = new (std::nothrow) svt_ctx();
+    if (c == nullptr) return SVT_E_NOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    c->cu_count = prop.multiProcessorCount;
+    c->clock_khz = prop.clockRate;
+    c->hbm_bytes = prop.totalGlobalMem;
+    snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+    c->max_grid = c->cu_count * svt::kMaxBlocksPerCu;
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipStreamCreate");
+    }
+    for (int i = 0; i < kSlots; ++i) {
+        Slot &s = c->slots[i];
+        svt_status st = SVT_OK;
+        if (hipEventCreate(&s.ev_start) != hipSuccess || hipEventCreate(&s.ev_end) != hipSuccess)
+            st = hip_fail(hipGetLastError(), "hipEventCreate");
+        if (st == SVT_OK)
+            st = dev_alloc(c, reinterpret_cast<void **>(&s.partials),
+                           sizeof(svt::BlockPartial) * c->max_grid + 2 * sizeof(uint32_t) * 64);
+        if (st == SVT_OK) {
+            s.counters = reinterpret_cast<uint32_t *>(s.partials + c->max_grid);
+            if (hipMemset(s.counters, 0, 2 * sizeof(uint32_t)) != hipSuccess)
+                st = hip_fail(hipGetLastError(), "hipMemset");
+        }
+        if (st == SVT_OK &&
+            hipHostMalloc(reinterpret_cast<void **>(&s.summary), sizeof(svt::SummaryDev),
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+            st = hip_fail(hipGetLastError(), "hipHostMalloc");
+        if (st != SVT_OK) {
+            *out = c;
+            svt_destroy(c);
+            *out = nullptr;
+            return st;
+        }
+        memset(s.summary, 0, sizeof(svt::SummaryDev));
+    }
+    *out = c;
+    return SVT_OK;
+}
+
+svt_status svt_destroy(svt_ctx *c)
+{
+    if (c == nullptr) return SVT_E_INVAL;
+    DeviceGuard g(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < kSlots; ++i) {
+        Slot &s = c->slots[i];
+        if (s.busy && s.ev_end) (void)hipEventSynchronize(s.ev_end);
+        if (s.ev_start) (void)hipEventDestroy(s.ev_start);
+        if (s.ev_end) (void)hipEventDestroy(s.ev_end);
+        if (s.partials) (void)hipFree(s.partials);
+        if (s.summary) (void)hipHostFree(s.summary);
+        if (s.stage.ptr) (void)hipFree(s.stage.ptr);
+        if (s.scan.ptr) (void)hipFree(s.scan.ptr);
+    }
+    if (c->coef) (void)hipFree(c->coef);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return SVT_OK;
+}
+
+svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef,
+                              const int32_t *offset, uint64_t chi2_cut)
+{
+    if (c == nullptr || coef == nullptr || offset == nullptr) return SVT_E_INVAL;
+    if (n_sectors < 1 || n_sectors > 256) return SVT_E_INVAL;
+    if (chi2_cut >= (1ull << 48)) return SVT_E_RANGE;
+    for (int s = 0; s < n_sectors; ++s)
+        for (int k = 0; k < 6; ++k) {
+            int64_t bound = llabs((long long)offset[s * 6 + k]);
+            for (int j = 0; j < 6; ++j) bound += llabs((long long)coef[(s * 6 + k) * 6 + j]) * 4095;
+            if (bound > 2147483647LL) return SVT_E_RANGE;
+        }
+    for (int i = 0; i < kSlots; ++i)
+        if (c->slots[i].busy) return SVT_E_STATE;
+    DeviceGuard g(c->device);
+    if (c->coef == nullptr) {
+        void *p = nullptr;
+        svt_status st = dev_alloc(c, &p, 256 * 42 * sizeof(int32_t));
+        if (st != SVT_OK) return st;
+        c->coef = static_cast<int32_t *>(p);
+        c->offset = c->coef + 256 * 36;
+    }
+    HIP_TRY(hipMemcpy(c->coef, coef, sizeof(int32_t) * 36 * n_sectors, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->offset, offset, sizeof(int32_t) * 6 * n_sectors, hipMemcpyHostToDevice));
+    c->n_sectors = n_sectors;
+    c->cut = chi2_cut;
+    c->loaded = true;
+    return SVT_OK;
+}
+
+svt_status svt_set_tuning(svt_ctx *c, const svt_tuning *t)
+{
+    if (c == nullptr || t == nullptr) return SVT_E_INVAL;
+    if (t->events_per_chunk < 0 || t->events_per_chunk > svt::kMaxEventsPerChunk) return SVT_E_INVAL;
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > svt::kMaxBlocksPerCu) return SVT_E_INVAL;
+    if (t->schedule < 0 || t->schedule > 2) return SVT_E_INVAL;
+    c->tuning.events_per_chunk = t->events_per_chunk;   // 0 = automatic
+    if (t->blocks_per_cu) c->tuning.blocks_per_cu = t->blocks_per_cu;
+    if (t->schedule) c->tuning.schedule = t->schedule;
+    return SVT_OK;
+}
+
+svt_status svt_get_tuning(svt_ctx *c, svt_tuning *t)
+{
+    if (c == nullptr || t == nullptr) return SVT_E_INVAL;
+    *t = c->tuning;
+    return SVT_OK;
+}
+
+svt_status svt_get_device_info(svt_ctx *c, svt_device_info *info)
+{
+    if (c == nullptr || info == nullptr) return SVT_E_INVAL;
+    memset(info, 0, sizeof *info);
+    info->compute_units = c->cu_count;
+    info->clock_khz = c->clock_khz;
+    info->hbm_bytes = (int64_t)c->hbm_bytes;
+    info->budget_bytes = (int64_t)c->budget;
+    info->used_bytes = (int64_t)c->used;
+    snprintf(info->arch, sizeof info->arch, "%s", c->arch);
+    return SVT_OK;
+}
+
+svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_results *res,
+                          void *hip_stream, svt_ticket *ticket)
+{
+    if (c == nullptr || b == nullptr || res == nullptr || ticket == nullptr) return SVT_E_INVAL;
+    if (!kind_ok(b->mem_kind) || !kind_ok(res->mem_kind)) return SVT_E_INVAL;
+    const int32_t ne = b->n_events, nr = b->n_roads, nh = b->n_hits;
+    if (ne < 0 || nr < 0 || nh < 0) return SVT_E_INVAL;
+    if (ne == 0 && nr != 0) return SVT_E_INVAL;
+    if (nr == 0 && nh != 0) return SVT_E_INVAL;
+    if (ne == INT32_MAX || nr == INT32_MAX) return SVT_E_INVAL;
+    if (b->road_offsets == nullptr) return SVT_E_INVAL;
+    if (nr > 0 && (b->sector == nullptr || b->nhits == nullptr || b->hit_offsets == nullptr ||
+                   b->xft == nullptr))
+        return SVT_E_INVAL;
+    if (nh > 0 && b->hits == nullptr) return SVT_E_INVAL;
+    if (nr > 0 && (res->ncomb == nullptr || res->npass == nullptr || res->best == nullptr ||
+                   res->chi2 == nullptr || res->params == nullptr || res->hit_index == nullptr))
+        return SVT_E_INVAL;
+    if (ne > 0 && res->ntracks == nullptr) return SVT_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(b->nhits) | reinterpret_cast<uintptr_t>(b->xft) |
+         reinterpret_cast<uintptr_t>(res->hit_index)) & 3u)
+        return SVT_E_INVAL;
+    if (!c->loaded) return SVT_E_STATE;
+
+    // a free ticket slot
+    const int si = (int)(c->next_ticket % kSlots);
+    Slot &s = c->slots[si];
+    if (s.busy) return SVT_E_AGAIN;
+
+    DeviceGuard g(c->device);
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+
+    // byte layout of inputs and results
+    const size_t b_ro = sizeof(int32_t) * ((size_t)ne + 1), b_sec = (size_t)nr,
+                 b_nh = 4 * (size_t)nr, b_ho = sizeof(int32_t) * ((size_t)nr + 1),
+                 b_hits = sizeof(int16_t) * (size_t)nh, b_xft = 4 * (size_t)nr;
+    const size_t b_ncomb = 4 * (size_t)nr, b_np = 4 * (size_t)nr, b_best = 4 * (size_t)nr,
+                 b_chi2 = 8 * (size_t)nr, b_par = 12 * (size_t)nr, b_hi = 4 * (size_t)nr,
+                 b_ntr = 4 * (size_t)ne, b_co = res->comb_offsets ? 8 * ((size_t)nr + 1) : 0;
+    const bool stage_in = b->mem_kind == SVT_MEM_PAGEABLE || b->mem_kind == SVT_MEM_PINNED;
+    const bool stage_out = res->mem_kind == SVT_MEM_PAGEABLE || res->mem_kind == SVT_MEM_PINNED;
+    size_t off = 0;
+    size_t o_ro = 0, o_sec = 0, o_nh = 0, o_ho = 0, o_hits = 0, o_xft = 0;
+    if (stage_in) {
+        o_ro = off; off = align_up(off + b_ro, 256);
+        o_sec = off; off = align_up(off + b_sec, 256);
+        o_nh = off; off = align_up(off + b_nh, 256);
+        o_ho = off; off = align_up(off + b_ho, 256);
+        o_hits = off; off = align_up(off + b_hits, 256);
+        o_xft = off; off = align_up(off + b_xft, 256);
+    }
+    size_t o_ncomb = 0, o_np = 0, o_best = 0, o_chi2 = 0, o_par = 0, o_hi = 0, o_ntr = 0, o_co = 0;
+    if (stage_out) {
+        o_ncomb = off; off = align_up(off + b_ncomb, 256);
+        o_np = off; off = align_up(off + b_np, 256);
+        o_best = off; off = align_up(off + b_best, 256);
+        o_chi2 = off; off = align_up(off + b_chi2, 256);
+        o_par = off; off = align_up(off + b_par, 256);
+        o_hi = off; off = align_up(off + b_hi, 256);
+        o_ntr = off; off = align_up(off + b_ntr, 256);
+        o_co = off; off = align_up(off + b_co, 256);
+    }
+    if (off) {
+        svt_status r = ensure(c, s.stage, off);
+        if (r != SVT_OK) return r;
+    }
+    if (res->comb_offsets) {
+        svt_status r = ensure(c, s.scan, svt::comb_offsets_scratch_bytes(nr));
+        if (r != SVT_OK) return r;
+    }
+    char *base = static_cast<char *>(s.stage.ptr);
+
+    svt::FitArgs a;
+    memset(&a, 0, sizeof a);
+    a.n_events = ne;
+    a.n_roads = nr;
+    a.n_hits = nh;
+    a.n_sectors = c->n_sectors;
+    a.coef = c->coef;
+    a.offset = c->offset;
+    a.cut_d = (double)c->cut;
+
+    HIP_TRY(hipEventRecord(s.ev_start, st));
+    if (stage_in) {
+        const hipMemcpyKind k = hipMemcpyHostToDevice;
+        HIP_TRY(hipMemcpyAsync(base + o_ro, b->road_offsets, b_ro, k, st));
+        if (nr) {
+            HIP_TRY(hipMemcpyAsync(base + o_sec, b->sector, b_sec, k, st));
+            HIP_TRY(hipMemcpyAsync(base + o_nh, b->nhits, b_nh, k, st));
+            HIP_TRY(hipMemcpyAsync(base + o_ho, b->hit_offsets, b_ho, k, st));
+            HIP_TRY(hipMemcpyAsync(base + o_xft, b->xft, b_xft, k, st));
+        }
+        if (nh) HIP_TRY(hipMemcpyAsync(base + o_hits, b->hits, b_hits, k, st));
+        a.road_offsets = reinterpret_cast<const int32_t *>(base + o_ro);
+        a.sector = reinterpret_cast<const uint8_t *>(base + o_sec);
+        a.nhits4 = reinterpret_cast<const uint32_t *>(base + o_nh);
+        a.hit_offsets = reinterpret_cast<const int32_t *>(base + o_ho);
+        a.hits = reinterpret_cast<const int16_t *>(base + o_hits);
+        a.xft2 = reinterpret_cast<const uint32_t *>(base + o_xft);
+    } else {
+        a.road_offsets = static_cast<const int32_t *>(device_view(b->road_offsets, b->mem_kind));
+        a.sector = static_cast<const uint8_t *>(device_view(b->sector, b->mem_kind));
+        a.nhits4 = static_cast<const uint32_t *>(device_view(b->nhits, b->mem_kind));
+        a.hit_offsets = static_cast<const int32_t *>(device_view(b->hit_offsets, b->mem_kind));
+        a.hits = static_cast<const int16_t *>(device_view(b->hits, b->mem_kind));
+        a.xft2 = static_cast<const uint32_t *>(device_view(b->xft, b->mem_kind));
+    }
+    int64_t *co_dev = nullptr;
+    if (stage_out) {
+        a.ncomb = reinterpret_cast<int32_t *>(base + o_ncomb);
+        a.npass = reinterpret_cast<int32_t *>(base + o_np);
+        a.best = reinterpret_cast<int32_t *>(base + o_best);
+        a.chi2 = reinterpret_cast<uint64_t *>(base + o_chi2);
+        a.params = reinterpret_cast<int32_t *>(base + o_par);
+        a.hit_index4 = reinterpret_cast<uint32_t *>(base + o_hi);
+        a.ntracks = reinterpret_cast<int32_t *>(base + o_ntr);
+        co_dev = res->comb_offsets ? reinterpret_cast<int64_t *>(base + o_co) : nullptr;
+    } else {
+        const int32_t k = res->mem_kind;
+        a.ncomb = static_cast<int32_t *>(const_cast<void *>(device_view(res->ncomb, k)));
+        a.npass = static_cast<int32_t *>(const_cast<void *>(device_view(res->npass, k)));
+        a.best = static_cast<int32_t *>(const_cast<void *>(device_view(res->best, k)));
+        a.chi2 = static_cast<uint64_t *>(const_cast<void *>(device_view(res->chi2, k)));
+        a.params = static_cast<int32_t *>(const_cast<void *>(device_view(res->params, k)));
+        a.hit_index4 = static_cast<uint32_t *>(const_cast<void *>(device_view(res->hit_index, k)));
+        a.ntracks = static_cast<int32_t *>(const_cast<void *>(device_view(res->ntracks, k)));
+        co_dev = static_cast<int64_t *>(const_cast<void *>(device_view(res->comb_offsets, k)));
+    }
+
+    const int epc = c->tuning.events_per_chunk > 0 ? c->tuning.events_per_chunk
+                                                   : auto_events_per_chunk(b);
+    const int64_t n_chunks = ne > 0 ? ((int64_t)ne + epc - 1) / epc : 0;
+    int64_t grid = (int64_t)c->cu_count * c->tuning.blocks_per_cu;
+    if (grid > n_chunks) grid = n_chunks;
+    if (grid < 1) grid = 1;
+    a.events_per_chunk = epc;
+    a.schedule = c->tuning.schedule;
+    a.partials = s.partials;
+    a.done = s.counters;
+    a.work = s.counters + 1;
+    a.summary = static_cast<svt::SummaryDev *>(const_cast<void *>(device_view(s.summary, SVT_MEM_MAPPED)));
+    a.seq = (uint32_t)c->next_ticket;
+    s.summary->seq = 0;
+    s.summary->status = SVT_E_DEVICE;
+
+    hipError_t e = svt::launch_fit(a, (int)grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
+    if (e != hipSuccess) return hip_fail(e, "fit kernel launch");
+    if (co_dev) {
+        e = svt::launch_comb_offsets(a.ncomb, co_dev, nr, static_cast<int64_t *>(s.scan.ptr), st);
+        if (e != hipSuccess) return hip_fail(e, "comb_offsets launch");
+    }
+    if (stage_out) {
+        const hipMemcpyKind k = hipMemcpyDeviceToHost;
+        if (nr) {
+            HIP_TRY(hipMemcpyAsync(res->ncomb, a.ncomb, b_ncomb, k, st));
+            HIP_TRY(hipMemcpyAsync(res->npass, a.npass, b_np, k, st));
+            HIP_TRY(hipMemcpyAsync(res->best, a.best, b_best, k, st));
+            HIP_TRY(hipMemcpyAsync(res->chi2, a.chi2, b_chi2, k, st));
+            HIP_TRY(hipMemcpyAsync(res->params, a.params, b_par, k, st));
+            HIP_TRY(hipMemcpyAsync(res->hit_index, a.hit_index4, b_hi, k, st));
+        }
+        if (ne) HIP_TRY(hipMemcpyAsync(res->ntracks, a.ntracks, b_ntr, k, st));
+        if (co_dev) HIP_TRY(hipMemcpyAsync(res->comb_offsets, co_dev, b_co, k, st));
+    }
+    HIP_TRY(hipEventRecord(s.ev_end, st));
+    s.busy = true;
+    s.ticket = c->next_ticket++;
+    *ticket = s.ticket;
+    return SVT_OK;
+}
+
+svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *out)
+{
+    if (c == nullptr || t <= 0) return SVT_E_INVAL;
+    Slot &s = c->slots[t % kSlots];
+    if (!s.busy || s.ticket != t) return SVT_E_INVAL;
+    DeviceGuard g(c->device);
+    if (wait_us < 0) {
+        HIP_TRY(hipEventSynchronize(s.ev_end));
+    } else {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (;;) {
+            hipError_t q = hipEventQuery(s.ev_end);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return hip_fail(q, "hipEventQuery");
+            const auto dt = std::chrono::duration_cast<std::chrono::microseconds>(
+                                std::chrono::steady_clock::now() - t0)
+                                .count();
+            if (dt >= wait_us) return SVT_E_AGAIN;
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+    }
+    const svt::SummaryDev d = *s.summary;
+    svt_status status = (d.seq == (uint32_t)t) ? (svt_status)d.status : SVT_E_DEVICE;
+    if (out) {
+        memset(out, 0, sizeof *out);
+        out->total_comb = d.total_comb;
+        out->total_pass = d.total_pass;
+        out->total_tracks = d.total_tracks;
+        out->err_road = d.err_road;
+        out->err_event = d.err_event;
+        out->status = status;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, s.ev_start, s.ev_end) == hipSuccess)
+            out->device_ns = (int64_t)((double)ms * 1e6);
+        else
+            (void)hipGetLastError();
+    }
+    s.busy = false;
+    s.ticket = -1;
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,287 @@
+"""ctypes binding of libsvt.so (declared in include/svt.h).
+
+Argument marshalling only: every step of the fit runs in the library's HIP
+kernels.  PyTorch supplies device memory and streams.  Importing this module
+loads the library and raises if it has not been built -- there is no other
+implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsvt.so")
+
+SVT_OK, SVT_E_INVAL, SVT_E_RANGE, SVT_E_NOMEM, SVT_E_STATE, SVT_E_AGAIN, SVT_E_DEVICE = \
+    0, -1, -2, -3, -4, -5, -6
+SVT_MEM_PAGEABLE, SVT_MEM_PINNED, SVT_MEM_MAPPED, SVT_MEM_DEVICE = 0, 1, 2, 3
+
+P = ctypes.c_void_p
+
+
+class svt_event_batch(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_int32), ("n_roads", ctypes.c_int32),
+                ("n_hits", ctypes.c_int32), ("mem_kind", ctypes.c_int32),
+                ("road_offsets", P), ("sector", P), ("nhits", P), ("hit_offsets", P),
+                ("hits", P), ("xft", P)]
+
+
+class svt_results(ctypes.Structure):
+    _fields_ = [("ncomb", P), ("npass", P), ("best", P), ("chi2", P), ("params", P),
+                ("hit_index", P), ("ntracks", P), ("comb_offsets", P),
+                ("mem_kind", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class svt_summary(ctypes.Structure):
+    _fields_ = [("total_comb", ctypes.c_int64), ("total_pass", ctypes.c_int64),
+                ("total_tracks", ctypes.c_int32), ("err_road", ctypes.c_int32),
+                ("err_event", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("device_ns", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class svt_tuning(ctypes.Structure):
+    _fields_ = [("events_per_chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class svt_device_info(ctypes.Structure):
+    _fields_ = [("compute_units", ctypes.c_int32), ("clock_khz", ctypes.c_int32),
+                ("hbm_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
+                ("used_bytes", ctypes.c_int64), ("arch", ctypes.c_char * 32)]
+
+
+# (name, restype, argtypes) of every exported entry point
+SIGNATURES = {
+    "svt_create": (ctypes.c_int32, [ctypes.POINTER(P), ctypes.c_int32, ctypes.c_size_t]),
+    "svt_destroy": (ctypes.c_int32, [P]),
+    "svt_load_constants": (ctypes.c_int32, [P, ctypes.c_int32, P, P, ctypes.c_uint64]),
+    "svt_fit_events": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch),
+                                        ctypes.POINTER(svt_results), P,
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "svt_result": (ctypes.c_int32, [P, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.POINTER(svt_summary)]),
+    "svt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "svt_last_error": (ctypes.c_char_p, []),
+    "svt_set_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
+    "svt_get_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
+    "svt_get_device_info": (ctypes.c_int32, [P, ctypes.POINTER(svt_device_info)]),
+}
+
+
+def _load():
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7).  Loading torch
+    # first makes libsvt.so bind to that same runtime by SONAME; loading
+    # libsvt.so first would bring in a second HIP/HSA runtime from /opt/rocm and
+    # the two cannot share the device in one process.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_1311_0380_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class SVTError(RuntimeError):
+    def __init__(self, status, what=""):
+        msg = lib.svt_status_string(status).decode()
+        if status == SVT_E_DEVICE:
+            msg += " (" + lib.svt_last_error().decode() + ")"
+        super().__init__(f"{what}: {msg}" if what else msg)
+        self.status = status
+
+
+def check(status, what=""):
+    if status != SVT_OK:
+        raise SVTError(status, what)
+    return status
+
+
+# ---------------------------------------------------------------------------
+# same-name wrappers of the C ABI
+# ---------------------------------------------------------------------------
+def svt_create(device: int = 0, hbm_budget_bytes: int = 0):
+    h = P()
+    check(lib.svt_create(ctypes.byref(h), int(device), int(hbm_budget_bytes)), "svt_create")
+    return h
+
+
+def svt_destroy(ctx):
+    return lib.svt_destroy(ctx)
+
+
+def svt_load_constants(ctx, coef: np.ndarray, offset: np.ndarray, chi2_cut: int) -> int:
+    coef = np.ascontiguousarray(coef, np.int32)
+    offset = np.ascontiguousarray(offset, np.int32)
+    return lib.svt_load_constants(ctx, int(coef.shape[0]), coef.ctypes.data, offset.ctypes.data,
+                                  ctypes.c_uint64(int(chi2_cut)))
+
+
+def svt_fit_events(ctx, batch: svt_event_batch, res: svt_results, stream=None):
+    t = ctypes.c_int64(0)
+    st = lib.svt_fit_events(ctx, ctypes.byref(batch), ctypes.byref(res),
+                            None if stream is None else P(stream), ctypes.byref(t))
+    return st, t.value
+
+
+def svt_result(ctx, ticket: int, wait_us: int = -1):
+    s = svt_summary()
+    st = lib.svt_result(ctx, int(ticket), int(wait_us), ctypes.byref(s))
+    return st, s
+
+
+def svt_status_string(status: int) -> str:
+    return lib.svt_status_string(int(status)).decode()
+
+
+def svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=0, schedule=0):
+    t = svt_tuning(int(events_per_chunk), int(blocks_per_cu), int(schedule), 0)
+    return lib.svt_set_tuning(ctx, ctypes.byref(t))
+
+
+def svt_get_tuning(ctx) -> dict:
+    t = svt_tuning()
+    check(lib.svt_get_tuning(ctx, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in t._fields_ if f != "reserved"}
+
+
+def svt_get_device_info(ctx) -> dict:
+    i = svt_device_info()
+    check(lib.svt_get_device_info(ctx, ctypes.byref(i)))
+    d = {f: getattr(i, f) for f, _ in i._fields_}
+    d["arch"] = d["arch"].decode()
+    return d
+
+
+# ---------------------------------------------------------------------------
+# torch-facing helpers (device memory and streams come from torch)
+# ---------------------------------------------------------------------------
+BATCH_FIELDS = ("road_offsets", "sector", "nhits", "hit_offsets", "hits", "xft")
+RESULT_FIELDS = ("ncomb", "npass", "best", "chi2", "params", "hit_index", "ntracks")
+
+
+@dataclass
+class DeviceBatch:
+    """A batch resident in device memory (torch tensors on cuda)."""
+    road_offsets: "torch.Tensor"
+    sector: "torch.Tensor"
+    nhits: "torch.Tensor"
+    hit_offsets: "torch.Tensor"
+    hits: "torch.Tensor"
+    xft: "torch.Tensor"
+
+    @property
+    def n_events(self):
+        return int(self.road_offsets.numel() - 1)
+
+    @property
+    def n_roads(self):
+        return int(self.sector.numel())
+
+    @property
+    def n_hits(self):
+        return int(self.hits.numel())
+
+    def struct(self, mem_kind=SVT_MEM_DEVICE) -> svt_event_batch:
+        return svt_event_batch(self.n_events, self.n_roads, self.n_hits, mem_kind,
+                               *[getattr(self, f).data_ptr() for f in BATCH_FIELDS])
+
+    def nbytes(self) -> int:
+        return sum(getattr(self, f).numel() * getattr(self, f).element_size() for f in BATCH_FIELDS)
+
+
+def to_device(batch, device="cuda") -> DeviceBatch:
+    import torch
+    return DeviceBatch(**{f: torch.from_numpy(np.ascontiguousarray(getattr(batch, f))).to(device)
+                          for f in BATCH_FIELDS})
+
+
+class DeviceResults:
+    """Result buffers (torch tensors) for a batch of n_events / n_roads."""
+
+    def __init__(self, n_events, n_roads, device="cuda", comb_offsets=False, pin=False):
+        import torch
+        kw = dict(device=device) if not pin else dict(pin_memory=True)
+        self.ncomb = torch.empty(n_roads, dtype=torch.int32, **kw)
+        self.npass = torch.empty(n_roads, dtype=torch.int32, **kw)
+        self.best = torch.empty(n_roads, dtype=torch.int32, **kw)
+        self.chi2 = torch.empty(n_roads, dtype=torch.int64, **kw)      # bit pattern of uint64
+        self.params = torch.empty((n_roads, 3), dtype=torch.int32, **kw)
+        self.hit_index = torch.empty((n_roads, 4), dtype=torch.uint8, **kw)
+        self.ntracks = torch.empty(n_events, dtype=torch.int32, **kw)
+        self.comb_offsets = torch.empty(n_roads + 1, dtype=torch.int64, **kw) if comb_offsets else None
+        self.mem_kind = SVT_MEM_PINNED if pin else SVT_MEM_DEVICE
+
+    def struct(self) -> svt_results:
+        return svt_results(*[getattr(self, f).data_ptr() for f in RESULT_FIELDS],
+                           self.comb_offsets.data_ptr() if self.comb_offsets is not None else None,
+                           self.mem_kind, 0)
+
+    def numpy(self) -> dict:
+        out = {f: getattr(self, f).cpu().numpy() for f in RESULT_FIELDS}
+        out["chi2"] = out["chi2"].view(np.uint64)
+        if self.comb_offsets is not None:
+            out["comb_offsets"] = self.comb_offsets.cpu().numpy()
+        return out
+
+
+class Context:
+    """Owns an svt_ctx; thin convenience layer over the C calls."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.handle = svt_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.handle:
+            svt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_constants(self, coef, offset, chi2_cut):
+        check(svt_load_constants(self.handle, coef, offset, chi2_cut), "svt_load_constants")
+
+    def submit(self, batch_struct: svt_event_batch, res_struct: svt_results, stream=None) -> int:
+        st, t = svt_fit_events(self.handle, batch_struct, res_struct, stream)
+        check(st, "svt_fit_events")
+        return t
+
+    def result(self, ticket: int, wait_us: int = -1):
+        return svt_result(self.handle, ticket, wait_us)
+
+    def fit(self, dbatch: DeviceBatch, res: DeviceResults = None, stream=None):
+        """Fit a device-resident batch on torch's current stream; blocks."""
+        import torch
+        if res is None:
+            res = DeviceResults(dbatch.n_events, dbatch.n_roads, device=dbatch.sector.device)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        t = self.submit(dbatch.struct(), res.struct(), stream)
+        st, summ = self.result(t, -1)
+        return st, summ, res
+
+    def set_tuning(self, **kw):
+        check(svt_set_tuning(self.handle, **kw), "svt_set_tuning")
+
+    def tuning(self):
+        return svt_get_tuning(self.handle)
+
+    def device_info(self):
+        return svt_get_device_info(self.handle)
