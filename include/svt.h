@@ -122,7 +122,7 @@ typedef struct {
 typedef struct {
     int32_t events_per_chunk;  /* events per work item (1..256); 0 = automatic    */
     int32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu (1..16)   */
-    int32_t schedule;          /* 1 = static round robin, 2 = dynamic work counter */
+    int32_t schedule;          /* 1 = cyclic (item w -> block w mod grid), 2 = blocked */
     int32_t reserved;
 } svt_tuning;
 

@@ -79,59 +79,87 @@ struct RowState {
     uint32_t np;         // passing combinations
 };
 
-// Inner loops with trip counts shared by the whole wavefront.
+// One combination: the three constraint rows from q (rows with layers 0..2)
+// plus column 3 times h3, chi2, pass count, running minimum (first index wins).
+__device__ __forceinline__ void combo(RowState &st, double q3, double q4, double q5, double h3,
+                                      double cut, uint32_t idx)
+{
+    const double y3 = fma(st.c3, h3, q3);
+    const double y4 = fma(st.c4, h3, q4);
+    const double y5 = fma(st.c5, h3, q5);
+    const double c = fma(y5, y5, fma(y4, y4, y3 * y3));
+    st.np += (c <= cut) ? 1u : 0u;
+    const bool better = c < st.bc;
+    st.bc = better ? c : st.bc;
+    st.bidx = better ? idx : st.bidx;
+}
+
+// Inner loops for a wavefront whose rows share n3 (= N3).  Rows are binned
+// with n3 as the major key, so n2 may still differ: every lane runs its own
+// n2 under the wavefront's largest n2 (n2w).
 template <int N3>
-__device__ __forceinline__ void row_loop_uniform(RowState &st, const double *s_hit, uint32_t p2,
-                                                 uint32_t n2, double cut)
+__device__ __forceinline__ void row_loop_uniform(RowState &st, const int16_t *s_hit, uint32_t p2,
+                                                 uint32_t n2, uint32_t n2w, double cut)
 {
     const uint32_t p3 = p2 + n2;
-    for (uint32_t i2 = 0; i2 < n2; ++i2) {
-        const double h2 = s_hit[p2 + i2];
-        const double q3 = fma(st.a3, h2, st.z3);
-        const double q4 = fma(st.a4, h2, st.z4);
-        const double q5 = fma(st.a5, h2, st.z5);
+    if constexpr (N3 <= 8) {
+        // the layer-3 hits stay in registers across the i2 loop
+        double h3[N3];
 #pragma unroll
-        for (int i3 = 0; i3 < N3; ++i3) {
-            const double h3 = s_hit[p3 + i3];
-            const double y3 = fma(st.c3, h3, q3);
-            const double y4 = fma(st.c4, h3, q4);
-            const double y5 = fma(st.c5, h3, q5);
-            const double c = fma(y5, y5, fma(y4, y4, y3 * y3));
-            st.np += (c <= cut) ? 1u : 0u;
-            if (c < st.bc) {
-                st.bc = c;
-                st.bidx = (i2 << 4) | (uint32_t)i3;
+        for (int i3 = 0; i3 < N3; ++i3) h3[i3] = (double)s_hit[p3 + i3];
+        for (uint32_t i2 = 0; i2 < n2w; ++i2) {
+            if (i2 < n2) {
+                const double h2 = (double)s_hit[p2 + i2];
+                const double q3 = fma(st.a3, h2, st.z3);
+                const double q4 = fma(st.a4, h2, st.z4);
+                const double q5 = fma(st.a5, h2, st.z5);
+#pragma unroll
+                for (int i3 = 0; i3 < N3; ++i3)
+                    combo(st, q3, q4, q5, h3[i3], cut, (i2 << 4) | (uint32_t)i3);
+            }
+        }
+    } else {
+        for (uint32_t i2 = 0; i2 < n2w; ++i2) {
+            if (i2 < n2) {
+                const double h2 = (double)s_hit[p2 + i2];
+                const double q3 = fma(st.a3, h2, st.z3);
+                const double q4 = fma(st.a4, h2, st.z4);
+                const double q5 = fma(st.a5, h2, st.z5);
+#pragma unroll 4
+                for (int i3 = 0; i3 < N3; ++i3)
+                    combo(st, q3, q4, q5, (double)s_hit[p3 + i3], cut, (i2 << 4) | (uint32_t)i3);
             }
         }
     }
 }
 
-// Inner loops for a wavefront whose rows have different (n2, n3).
-__device__ __forceinline__ void row_loop_mixed(RowState &st, const double *s_hit, uint32_t p2,
+// Inner loops for a wavefront whose rows have different (n2, n3): indices are
+// clamped into the row's lists and combinations past the row's end get a
+// chi2 that neither passes nor wins.
+__device__ __forceinline__ void row_loop_mixed(RowState &st, const int16_t *s_hit, uint32_t p2,
                                                uint32_t n2, uint32_t n3, uint32_t n2w,
                                                uint32_t n3w, double cut)
 {
     const uint32_t p3 = p2 + n2;
+    const double never = cut + 2.0;
     for (uint32_t i2 = 0; i2 < n2w; ++i2) {
-        if (i2 < n2) {
-            const double h2 = s_hit[p2 + i2];
-            const double q3 = fma(st.a3, h2, st.z3);
-            const double q4 = fma(st.a4, h2, st.z4);
-            const double q5 = fma(st.a5, h2, st.z5);
-            for (uint32_t i3 = 0; i3 < n3w; ++i3) {
-                if (i3 < n3) {
-                    const double h3 = s_hit[p3 + i3];
-                    const double y3 = fma(st.c3, h3, q3);
-                    const double y4 = fma(st.c4, h3, q4);
-                    const double y5 = fma(st.c5, h3, q5);
-                    const double c = fma(y5, y5, fma(y4, y4, y3 * y3));
-                    st.np += (c <= cut) ? 1u : 0u;
-                    if (c < st.bc) {
-                        st.bc = c;
-                        st.bidx = (i2 << 4) | i3;
-                    }
-                }
-            }
+        const uint32_t i2c = i2 < n2 ? i2 : n2 - 1;
+        const double h2 = (double)s_hit[p2 + i2c];
+        const double q3 = fma(st.a3, h2, st.z3);
+        const double q4 = fma(st.a4, h2, st.z4);
+        const double q5 = fma(st.a5, h2, st.z5);
+        for (uint32_t i3 = 0; i3 < n3w; ++i3) {
+            const uint32_t i3c = i3 < n3 ? i3 : n3 - 1;
+            const double h3 = (double)s_hit[p3 + i3c];
+            const double y3 = fma(st.c3, h3, q3);
+            const double y4 = fma(st.c4, h3, q4);
+            const double y5 = fma(st.c5, h3, q5);
+            double c = fma(y5, y5, fma(y4, y4, y3 * y3));
+            c = (i2 < n2 && i3 < n3) ? c : never;
+            st.np += (c <= cut) ? 1u : 0u;
+            const bool better = c < st.bc;
+            st.bc = better ? c : st.bc;
+            st.bidx = better ? ((i2 << 4) | i3) : st.bidx;
         }
     }
 }
@@ -148,12 +176,13 @@ struct Acc {
 };
 
 struct Shared {
-    double hit[kHitCap];
-    uint64_t row[kRowCap];
-    double base[3][kSubRoads];
-    unsigned long long key[kSubRoads];
-    uint32_t np[kSubRoads];
-    uint32_t hb[kSubRoads];
+    double base[3][kSubRoads];              // b + A[:,4] x4 + A[:,5] x5, rows 3..5
+    unsigned long long key[kSubRoads];      // best key of each road
+    uint32_t n4[kSubRoads];                 // packed hit counts of each road
+    uint32_t np[kSubRoads];                 // passing combinations of each road
+    uint16_t hb[kSubRoads];                 // first staged hit of each road
+    uint16_t row[kRowCap];                  // road | i0 << 8 | i1 << 12, binned by (n2, n3)
+    int16_t hit[kHitCap];                   // staged hit words
     uint32_t bin[kBins];
     int32_t evro[kMaxEventsPerChunk + 1];
     uint32_t evcnt[kMaxEventsPerChunk];
@@ -162,16 +191,24 @@ struct Shared {
     int32_t misc[4];
 };
 
+constexpr int kStage = kHitCap / kBlock;    // staged hits per thread
+
 // Process the roads [s, rb) of the current chunk starting at road s; returns
 // how many roads were fitted (at least one when s < rb).
-__device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, const int32_t *s_ci,
-                           int32_t s, int32_t rb, int32_t n_roads, int32_t n_hits,
-                           int32_t n_sectors, int32_t ne, double cut, Acc &acc)
+__device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int32_t s, int32_t rb,
+                           int32_t n_roads, int32_t n_hits, int32_t n_sectors, int32_t ne,
+                           double cut, Acc &acc)
 {
     const int tid = threadIdx.x;
     const int32_t r = s + tid;
     const bool inr = r < rb;
 
+    // one round of loads: the sub-chunk's hit range (uniform), each thread's
+    // road, and a speculative copy of the hits the next kSubRoads roads hold
+    const int32_t s_end = min(rb, s + kSubRoads);
+    const int32_t hs = clampi(a.hit_offsets[s], 0, n_hits);
+    const int32_t he = clampi(a.hit_offsets[s_end], hs, n_hits);
+    const int32_t t_pre = min(he - hs, kHitCap);
     uint32_t sec = 0, nh4 = 0, x2 = 0;
     int32_t h0 = 0, h1 = 0;
     if (inr) {
@@ -181,6 +218,13 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, cons
         h1 = a.hit_offsets[r + 1];
         x2 = a.xft2[r];
     }
+    int16_t v[kStage];
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+        const int t = tid + q * kBlock;
+        v[q] = t < t_pre ? a.hits[hs + t] : (int16_t)0;
+    }
+
     const uint32_t n0 = nh4 & 255u, n1 = (nh4 >> 8) & 255u, n2 = (nh4 >> 16) & 255u,
                    n3 = nh4 >> 24;
     const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
@@ -204,53 +248,62 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, cons
         S.misc[1] = (int32_t)(hb + nh);           // hits of the sub-chunk
         S.misc[3] = (int32_t)(rbase + rows);      // rows of the sub-chunk
     }
-    if (tid == 0) S.misc[2] = clampi(h0, 0, n_hits);
+    const uint32_t bkey = n3 * 17u + n2;   // n3 major: wavefronts share n3
+    uint32_t boff = 0;
     if (active) {
-        S.hb[tid] = hb;
+        S.hb[tid] = (uint16_t)hb;
+        S.n4[tid] = ok ? nh4 : 0u;
         S.sec[tid] = (uint8_t)(ok ? sec : 0u);
         S.key[tid] = ~0ull;
         S.np[tid] = 0;
-    }
-    for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;
-    __syncthreads();
-
-    const int32_t T = S.misc[1], hs = S.misc[2], total_rows = S.misc[3];
-    const uint32_t bkey = n2 * 17u + n3;
-    uint32_t boff = 0;
-    if (active && rows) boff = atomicAdd(&S.bin[bkey], rows);
-
-    // stage the sub-chunk's hits (contiguous in the batch), check their range
-    for (int t = tid; t < T; t += kBlock) {
-        const int32_t g = hs + t;
-        const int32_t h = g < n_hits ? (int32_t)a.hits[g] : 0;
-        S.hit[t] = (double)h;
-        if (h < 0 || h >= 4096) {
-            int lo = 0, hi = L;     // last road with hb <= t
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if ((int32_t)S.hb[mid] <= t) lo = mid; else hi = mid;
-            }
-            acc.err_road = min(acc.err_road, (uint32_t)(s + lo));
+        if (rows) boff = atomicAdd(&S.bin[bkey], rows);
+        if (ok) {
+            // constant part of the constraint rows, exact in int32
+            const double *cs = s_cd + sec * kCstStride;
+            const int32_t *cb = reinterpret_cast<const int32_t *>(cs) + kCstIntB;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                S.base[k][tid] = fma(cs[15 + k], (double)xb, fma(cs[12 + k], (double)xa, (double)cb[k]));
         }
     }
-    // constant part of the constraint rows: b + A[:,4] x4 + A[:,5] x5
-    if (active && ok) {
-        const double *cs = s_cd + sec * kCstDoubles;
-        const double x4 = (double)xa, x5 = (double)xb;
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            S.base[k][tid] = fma(cs[15 + k], x5, fma(cs[12 + k], x4, cs[18 + k]));
+    for (int q = 0; q < kStage; ++q) {
+        const int t = tid + q * kBlock;
+        if (t < t_pre) S.hit[t] = v[q];
     }
     __syncthreads();
-
+    const int32_t T = S.misc[1], total_rows = S.misc[3];
+    // range of the hit words: the speculative copy, then hits it did not
+    // cover (only possible with inconsistent offsets), each checked by the
+    // thread that holds it
+    int32_t bad_t = INT32_MAX;
+#pragma unroll
+    for (int q = 0; q < kStage; ++q) {
+        const int t = tid + q * kBlock;
+        if (t < T && t < t_pre && (v[q] < 0 || v[q] >= 4096)) bad_t = min(bad_t, t);
+    }
+    for (int t = t_pre + tid; t < T; t += kBlock) {
+        const int32_t g = hs + t;
+        const int16_t h = g < n_hits ? a.hits[g] : (int16_t)0;
+        S.hit[t] = h;
+        if (h < 0 || h >= 4096) bad_t = min(bad_t, t);
+    }
+    if (bad_t != INT32_MAX) {
+        int lo = 0, hi = L;     // last road with hb <= bad_t
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if ((int32_t)S.hb[mid] <= bad_t) lo = mid; else hi = mid;
+        }
+        acc.err_road = min(acc.err_road, (uint32_t)(s + lo));
+    }
     // bin starts: exclusive scan of the 289 bins by wave 0
     if (tid < 64) {
-        uint32_t v[5], loc = 0;
+        uint32_t vb[5], loc = 0;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const int b = tid * 5 + q;
-            v[q] = b < kBins ? S.bin[b] : 0u;
-            loc += v[q];
+            vb[q] = b < kBins ? S.bin[b] : 0u;
+            loc += vb[q];
         }
         const uint64_t incl = wave_incl_scan(loc, tid);
         uint32_t run = (uint32_t)incl - loc;
@@ -258,7 +311,7 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, cons
         for (int q = 0; q < 5; ++q) {
             const int b = tid * 5 + q;
             if (b < kBins) S.bin[b] = run;
-            run += v[q];
+            run += vb[q];
         }
     }
     __syncthreads();
@@ -266,28 +319,26 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, cons
     // rows of the road, in (i0, i1) order, at its place in the binned list
     if (active && rows) {
         uint32_t w = S.bin[bkey] + boff;
-        const uint64_t common = ((uint64_t)(hb + n0 + n1) << 24) | ((uint64_t)n2 << 36) |
-                                ((uint64_t)n3 << 41) | ((uint64_t)tid << 46);
         for (uint32_t i0 = 0; i0 < n0; ++i0)
             for (uint32_t i1 = 0; i1 < n1; ++i1, ++w)
-                S.row[w] = common | (uint64_t)(hb + i0) | ((uint64_t)(hb + n0 + i1) << 12) |
-                           ((uint64_t)i0 << 54) | ((uint64_t)i1 << 58);
+                S.row[w] = (uint16_t)(tid | (i0 << 8) | (i1 << 12));
     }
     __syncthreads();
+    for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;   // ready for the next sub-chunk
 
     // B: every combination of every row
     for (int idx0 = 0; idx0 < total_rows; idx0 += kBlock) {
         if (idx0 + (tid & ~63) >= total_rows) continue;   // whole wavefront idle
         const int idx = idx0 + tid;
         const bool act = idx < total_rows;
-        const uint64_t d = S.row[act ? idx : total_rows - 1];
-        const uint32_t p0 = (uint32_t)d & 0xFFFu, p1 = (uint32_t)(d >> 12) & 0xFFFu,
-                       p2 = (uint32_t)(d >> 24) & 0xFFFu;
-        const uint32_t rn2 = (uint32_t)(d >> 36) & 31u, rn3 = (uint32_t)(d >> 41) & 31u;
-        const uint32_t j = (uint32_t)(d >> 46) & 255u;
-        const uint32_t i0 = (uint32_t)(d >> 54) & 15u, i1 = (uint32_t)(d >> 58) & 15u;
-        const double *cs = s_cd + (uint32_t)S.sec[j] * kCstDoubles;
-        const double h0v = S.hit[p0], h1v = S.hit[p1];
+        const uint32_t d = S.row[act ? idx : total_rows - 1];
+        const uint32_t j = d & 255u, i0 = (d >> 8) & 15u, i1 = (d >> 12) & 15u;
+        const uint32_t rn = S.n4[j], hbj = S.hb[j];
+        const uint32_t rn0 = rn & 255u, rn1 = (rn >> 8) & 255u, rn2 = (rn >> 16) & 255u,
+                       rn3 = rn >> 24;
+        const uint32_t p2 = hbj + rn0 + rn1;
+        const double *cs = s_cd + (uint32_t)S.sec[j] * kCstStride;
+        const double h0v = (double)S.hit[hbj + i0], h1v = (double)S.hit[hbj + rn0 + i1];
         RowState st;
         st.z3 = fma(cs[3], h1v, fma(cs[0], h0v, S.base[0][j]));
         st.z4 = fma(cs[4], h1v, fma(cs[1], h0v, S.base[1][j]));
@@ -301,33 +352,33 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, cons
         st.bc = cut + 1.0;
         st.bidx = 0xFFFFFFFFu;
         st.np = 0;
-        const uint32_t nn = (rn2 << 8) | rn3;
-        const uint32_t first = __builtin_amdgcn_readfirstlane(nn);
-        if (__all(nn == first)) {
-            const uint32_t un2 = first >> 8;
-            switch (first & 31u) {
-            case 1: row_loop_uniform<1>(st, S.hit, p2, un2, cut); break;
-            case 2: row_loop_uniform<2>(st, S.hit, p2, un2, cut); break;
-            case 3: row_loop_uniform<3>(st, S.hit, p2, un2, cut); break;
-            case 4: row_loop_uniform<4>(st, S.hit, p2, un2, cut); break;
-            case 5: row_loop_uniform<5>(st, S.hit, p2, un2, cut); break;
-            case 6: row_loop_uniform<6>(st, S.hit, p2, un2, cut); break;
-            case 7: row_loop_uniform<7>(st, S.hit, p2, un2, cut); break;
-            case 8: row_loop_uniform<8>(st, S.hit, p2, un2, cut); break;
-            case 9: row_loop_uniform<9>(st, S.hit, p2, un2, cut); break;
-            case 10: row_loop_uniform<10>(st, S.hit, p2, un2, cut); break;
-            case 11: row_loop_uniform<11>(st, S.hit, p2, un2, cut); break;
-            case 12: row_loop_uniform<12>(st, S.hit, p2, un2, cut); break;
-            case 13: row_loop_uniform<13>(st, S.hit, p2, un2, cut); break;
-            case 14: row_loop_uniform<14>(st, S.hit, p2, un2, cut); break;
-            case 15: row_loop_uniform<15>(st, S.hit, p2, un2, cut); break;
-            case 16: row_loop_uniform<16>(st, S.hit, p2, un2, cut); break;
+        // binned order: the last lane holds the largest (n3, n2) of the wavefront
+        const uint32_t n3f = __builtin_amdgcn_readfirstlane(rn3);
+        const uint32_t n3l = __builtin_amdgcn_readlane(rn3, 63);
+        if (n3f == n3l) {
+            const uint32_t n2w = __builtin_amdgcn_readlane(rn2, 63);
+            switch (n3f) {
+            case 1: row_loop_uniform<1>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 2: row_loop_uniform<2>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 3: row_loop_uniform<3>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 4: row_loop_uniform<4>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 5: row_loop_uniform<5>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 6: row_loop_uniform<6>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 7: row_loop_uniform<7>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 8: row_loop_uniform<8>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 9: row_loop_uniform<9>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 10: row_loop_uniform<10>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 11: row_loop_uniform<11>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 12: row_loop_uniform<12>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 13: row_loop_uniform<13>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 14: row_loop_uniform<14>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 15: row_loop_uniform<15>(st, S.hit, p2, rn2, n2w, cut); break;
+            case 16: row_loop_uniform<16>(st, S.hit, p2, rn2, n2w, cut); break;
             default: break;
             }
         } else {
-            const uint32_t n2w = wave_max_u32(rn2), n3w = wave_max_u32(rn3);
-            row_loop_mixed(st, S.hit, p2, rn2, rn3, __builtin_amdgcn_readfirstlane(n2w),
-                           __builtin_amdgcn_readfirstlane(n3w), cut);
+            const uint32_t n2w = wave_max_u32(rn2);
+            row_loop_mixed(st, S.hit, p2, rn2, rn3, __builtin_amdgcn_readfirstlane(n2w), n3l, cut);
         }
         if (act) {
             if (st.bidx != 0xFFFFFFFFu) {
@@ -360,13 +411,15 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, cons
                                    (uint32_t)(int32_t)S.hit[hb + n0 + n1 + i2],
                                    (uint32_t)(int32_t)S.hit[hb + n0 + n1 + n2 + i3],
                                    (uint32_t)xa, (uint32_t)xb};
-            const int32_t *ci = s_ci + sec * kCstInts;
+            // parameter rows 0..2, exact in int32 by the load-time bound
+            const int32_t *ci = reinterpret_cast<const int32_t *>(s_cd + sec * kCstStride);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                uint32_t v = (uint32_t)ci[18 + k];   // exact in int32 by the load-time bound
+                uint32_t acc32 = (uint32_t)ci[kCstIntPB + k];
 #pragma unroll
-                for (int col = 0; col < 6; ++col) v += (uint32_t)ci[col * 3 + k] * x[col];
-                p[k] = (int32_t)v;
+                for (int col = 0; col < 6; ++col)
+                    acc32 += (uint32_t)ci[kCstIntP + col * 3 + k] * x[col];
+                p[k] = (int32_t)acc32;
             }
         }
         a.ncomb[r] = ok ? (int32_t)(n0 * n1 * n2 * n3) : 0;
@@ -395,7 +448,25 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, cons
     return L;
 }
 
-__global__ void __launch_bounds__(kBlock) fit_kernel(FitArgs a)
+// Static schedules (no shared counter): 1 = cyclic (chunk c -> block c mod
+// grid), 2 = blocked (block b owns a contiguous range of chunks).
+__device__ __forceinline__ void chunk_range(int32_t n_chunks, int32_t schedule, int32_t &first,
+                                            int32_t &step, int32_t &last)
+{
+    if (schedule == 2) {
+        const int64_t g = gridDim.x, b = blockIdx.x;
+        first = (int32_t)((int64_t)n_chunks * b / g);
+        last = (int32_t)((int64_t)n_chunks * (b + 1) / g);
+        step = 1;
+    } else {
+        first = blockIdx.x;
+        last = n_chunks;
+        step = gridDim.x;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+fit_kernel(FitArgs a)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ Shared S;
@@ -409,24 +480,27 @@ __global__ void __launch_bounds__(kBlock) fit_kernel(FitArgs a)
     }
     const int32_t n_sectors = a.n_sectors;
     double *s_cd = reinterpret_cast<double *>(s_dyn);
-    int32_t *s_ci = reinterpret_cast<int32_t *>(s_dyn + (size_t)n_sectors * kCstDoubles * 8);
 
-    // sector constants -> LDS: constraint rows as fp64, parameter rows as int32
+    // sector constants -> LDS: constraint rows 3..5 as fp64 columns, their
+    // offsets as int32; parameter rows 0..2 and offsets as int32
     for (int i = tid; i < n_sectors * 6; i += kBlock) {
         const int sct = i / 6, col = i - sct * 6;
+        int32_t *ci = reinterpret_cast<int32_t *>(s_cd + sct * kCstStride);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            s_cd[sct * kCstDoubles + col * 3 + k] = (double)a.coef[(sct * 6 + 3 + k) * 6 + col];
-            s_ci[sct * kCstInts + col * 3 + k] = a.coef[(sct * 6 + k) * 6 + col];
+            s_cd[sct * kCstStride + col * 3 + k] = (double)a.coef[(sct * 6 + 3 + k) * 6 + col];
+            ci[kCstIntP + col * 3 + k] = a.coef[(sct * 6 + k) * 6 + col];
         }
     }
     for (int sct = tid; sct < n_sectors; sct += kBlock) {
+        int32_t *ci = reinterpret_cast<int32_t *>(s_cd + sct * kCstStride);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            s_cd[sct * kCstDoubles + 18 + k] = (double)a.offset[sct * 6 + 3 + k];
-            s_ci[sct * kCstInts + 18 + k] = a.offset[sct * 6 + k];
+            ci[kCstIntB + k] = a.offset[sct * 6 + 3 + k];
+            ci[kCstIntPB + k] = a.offset[sct * 6 + k];
         }
     }
+    for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;
     __syncthreads();
 
     Acc acc;
@@ -434,45 +508,29 @@ __global__ void __launch_bounds__(kBlock) fit_kernel(FitArgs a)
     const int32_t E = a.events_per_chunk;
     const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
 
-    int32_t c;
-    if (a.schedule == 2) {
-        if (tid == 0) S.misc[0] = (int32_t)atomicAdd(a.work, 1u);
-        __syncthreads();
-        c = S.misc[0];
-        __syncthreads();
-    } else {
-        c = blockIdx.x;
-    }
-    while (c < n_chunks) {
+    int32_t c_first, c_step, c_last;
+    chunk_range(n_chunks, a.schedule, c_first, c_step, c_last);
+    for (int32_t c = c_first; c < c_last; c += c_step) {
         const int32_t e0 = c * E;
         const int32_t ne = min(E, n_events - e0);
+        const int32_t ra = clampi(a.road_offsets[e0], 0, n_roads);
+        const int32_t rb = clampi(a.road_offsets[e0 + ne], ra, n_roads);
         for (int i = tid; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
         for (int i = tid; i < ne; i += kBlock) S.evcnt[i] = 0;
         __syncthreads();
+        for (int32_t s = ra; s < rb;)
+            s += process_sub(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc);
         for (int i = tid; i < ne; i += kBlock) {
             const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
             const bool bad = lo < 0 || hi < lo || hi > n_roads || (e == 0 && lo != 0) ||
                              (e == n_events - 1 && hi != n_roads);
             if (bad) acc.err_event = min(acc.err_event, (uint32_t)e);
+            a.ntracks[e] = (int32_t)S.evcnt[i];
         }
-        const int32_t ra = clampi(S.evro[0], 0, n_roads);
-        const int32_t rb = clampi(S.evro[ne], ra, n_roads);
-        for (int32_t s = ra; s < rb;)
-            s += process_sub(a, S, s_cd, s_ci, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc);
         __syncthreads();
-        for (int i = tid; i < ne; i += kBlock) a.ntracks[e0 + i] = (int32_t)S.evcnt[i];
-        __syncthreads();
-        if (a.schedule == 2) {
-            if (tid == 0) S.misc[0] = (int32_t)atomicAdd(a.work, 1u);
-            __syncthreads();
-            c = S.misc[0];
-            __syncthreads();
-        } else {
-            c += gridDim.x;
-        }
     }
 
-    // block partials -> last block -> request summary
+    // block sums -> host-mapped partials (the host reduces them)
     const int lane = tid & 63, wid = tid >> 6;
     uint64_t comb = acc.comb, pass = acc.pass;
     uint32_t trk = acc.tracks, er = acc.err_road, ee = acc.err_event;
@@ -485,7 +543,6 @@ __global__ void __launch_bounds__(kBlock) fit_kernel(FitArgs a)
         ee = min(ee, (uint32_t)__shfl_xor(ee, off, 64));
     }
     __shared__ BlockPartial s_part[kWaves];
-    __shared__ int s_last;
     if (lane == 0) s_part[wid] = BlockPartial{comb, pass, trk, er, ee, 0};
     __syncthreads();
     if (tid == 0) {
@@ -497,59 +554,8 @@ __global__ void __launch_bounds__(kBlock) fit_kernel(FitArgs a)
             p.err_road = min(p.err_road, s_part[w].err_road);
             p.err_event = min(p.err_event, s_part[w].err_event);
         }
+        p.seq = a.seq;
         a.partials[blockIdx.x] = p;
-        __threadfence();
-        const uint32_t prev = atomicAdd(a.done, 1u);
-        s_last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    comb = 0;
-    pass = 0;
-    trk = 0;
-    er = 0xFFFFFFFFu;
-    ee = 0xFFFFFFFFu;
-    for (uint32_t b = tid; b < gridDim.x; b += kBlock) {
-        const BlockPartial p = a.partials[b];
-        comb += p.comb;
-        pass += p.pass;
-        trk += p.tracks;
-        er = min(er, p.err_road);
-        ee = min(ee, p.err_event);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        comb += __shfl_xor(comb, off, 64);
-        pass += __shfl_xor(pass, off, 64);
-        trk += __shfl_xor(trk, off, 64);
-        er = min(er, (uint32_t)__shfl_xor(er, off, 64));
-        ee = min(ee, (uint32_t)__shfl_xor(ee, off, 64));
-    }
-    __syncthreads();
-    if (lane == 0) s_part[wid] = BlockPartial{comb, pass, trk, er, ee, 0};
-    __syncthreads();
-    if (tid == 0) {
-        BlockPartial p = s_part[0];
-        for (int w = 1; w < kWaves; ++w) {
-            p.comb += s_part[w].comb;
-            p.pass += s_part[w].pass;
-            p.tracks += s_part[w].tracks;
-            p.err_road = min(p.err_road, s_part[w].err_road);
-            p.err_event = min(p.err_event, s_part[w].err_event);
-        }
-        SummaryDev *out = a.summary;
-        out->total_comb = (int64_t)p.comb;
-        out->total_pass = (int64_t)p.pass;
-        out->total_tracks = (int32_t)p.tracks;
-        out->err_road = p.err_road == 0xFFFFFFFFu ? -1 : (int32_t)p.err_road;
-        out->err_event = p.err_event == 0xFFFFFFFFu ? -1 : (int32_t)p.err_event;
-        out->status = (p.err_road != 0xFFFFFFFFu || p.err_event != 0xFFFFFFFFu) ? -2 : 0;
-        *a.done = 0;
-        *a.work = 0;
-        __threadfence_system();
-        out->seq = a.seq;
-        __threadfence_system();
     }
 }
 

@@ -8,42 +8,39 @@ namespace svt {
 // Launch geometry of the fused fit kernel.
 constexpr int kBlock = 256;        // threads per block (4 wave64)
 constexpr int kSubRoads = 256;     // roads per sub-chunk: one thread per road
-constexpr int kHitCap = 3072;      // hits staged in LDS per sub-chunk
+constexpr int kHitCap = 4096;      // hits staged in LDS per sub-chunk
 constexpr int kRowCap = 2048;      // (i0, i1) rows per sub-chunk
 constexpr int kMaxEventsPerChunk = 256;
 constexpr int kMaxBlocksPerCu = 16;
-// Per sector, in dynamic LDS: 24 doubles (constraint rows 3..5: 6 columns x 3
-// rows, then 3 offsets, 3 pad) followed by 24 int32 (parameter rows 0..2:
-// 6 columns x 3 rows, then 3 offsets, 3 pad).
-constexpr int kCstDoubles = 24;
-constexpr int kCstInts = 24;
-constexpr int kCstBytesPerSector = kCstDoubles * 8 + kCstInts * 4;
+constexpr int kTargetRoadsPerChunk = 256;
+// Per sector, in dynamic LDS (stride kCstStride doubles = 256 bytes):
+//   doubles [0, 18)   constraint rows 3..5, 6 columns x 3 rows ([col * 3 + row])
+//   int32   [36, 39)  offsets of rows 3..5
+//   int32   [40, 58)  parameter rows 0..2, 6 columns x 3 rows ([col * 3 + row])
+//   int32   [58, 61)  offsets of rows 0..2
+constexpr int kCstDoubles = 18;
+constexpr int kCstStride = 32;
+constexpr int kCstBytesPerSector = kCstStride * 8;
+constexpr int kCstIntB = 36;      // int32 index of the constraint offsets
+constexpr int kCstIntP = 40;      // int32 index of the parameter columns
+constexpr int kCstIntPB = 58;     // int32 index of the parameter offsets
 
 // Sizes of a batch when they are read from device memory (graph replay).
 struct Sizes {
     int32_t n_events, n_roads, n_hits, pad;
 };
 
-// Per-block partial sums of a request, reduced by the last block.
+// Partial sums of one block, written by the block into host-mapped memory and
+// reduced by the host when the request completes (no device-wide atomics or
+// fences: contended atomics serialize and device-scope fences write back and
+// invalidate an XCD's whole L2).
 struct BlockPartial {
     uint64_t comb;
     uint64_t pass;
     uint32_t tracks;
     uint32_t err_road;    // lowest bad road, 0xFFFFFFFF if none
     uint32_t err_event;   // lowest bad event, 0xFFFFFFFF if none
-    uint32_t pad;
-};
-
-// Request summary written by the last block (host-mapped memory).
-struct SummaryDev {
-    int64_t total_comb;
-    int64_t total_pass;
-    int32_t total_tracks;
-    int32_t err_road;
-    int32_t err_event;
-    int32_t status;
-    uint32_t seq;          // request sequence number, written last
-    uint32_t pad;
+    uint32_t seq;         // request sequence number
 };
 
 struct FitArgs {
@@ -71,12 +68,9 @@ struct FitArgs {
     int32_t *ntracks;
     // launch shape
     int32_t events_per_chunk;
-    int32_t schedule;           // 1 static, 2 dynamic
-    // request bookkeeping (device)
-    BlockPartial *partials;     // [gridDim.x]
-    uint32_t *done;             // blocks finished; reset by the last block
-    uint32_t *work;             // dynamic work counter; reset by the last block
-    SummaryDev *summary;        // written by the last block
+    int32_t schedule;           // 1 cyclic, 2 blocked
+    // request bookkeeping
+    BlockPartial *partials;     // host-mapped, [gridDim.x]
     uint32_t seq;
 };
 

@@ -43,9 +43,8 @@ struct Slot {
     bool busy = false;
     svt_ticket ticket = -1;
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
-    svt::BlockPartial *partials = nullptr;   // device [max grid]
-    uint32_t *counters = nullptr;            // device [2]: done, work
-    svt::SummaryDev *summary = nullptr;      // host-mapped
+    svt::BlockPartial *partials = nullptr;   // host-mapped [max grid]
+    int grid = 0;                            // blocks of the request in flight
     DevBuf stage;                            // device staging for host inputs / results
     DevBuf scan;                             // comb_offsets scratch
     svt_status host_status = SVT_OK;
@@ -72,7 +71,7 @@ struct svt_ctx {
     // requests
     Slot slots[kSlots];
     svt_ticket next_ticket = 1;
-    svt_tuning tuning{0, 2, 1, 0};
+    svt_tuning tuning{0, 3, 1, 0};  // auto chunk, 3 blocks/CU, cyclic
 };
 
 namespace {
@@ -149,7 +148,7 @@ int auto_events_per_chunk(const svt_event_batch *b)
 {
     if (b->n_events <= 0) return 1;
     const double rpe = (double)b->n_roads / (double)b->n_events;
-    int e = rpe > 0 ? (int)(256.0 / rpe) : 256;
+    int e = rpe > 0 ? (int)((double)svt::kTargetRoadsPerChunk / rpe + 0.5) : 256;
     if (e < 1) e = 1;
     if (e > svt::kMaxEventsPerChunk) e = svt::kMaxEventsPerChunk;
     return e;
@@ -208,16 +207,9 @@ svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes)
         svt_status st = SVT_OK;
         if (hipEventCreate(&s.ev_start) != hipSuccess || hipEventCreate(&s.ev_end) != hipSuccess)
             st = hip_fail(hipGetLastError(), "hipEventCreate");
-        if (st == SVT_OK)
-            st = dev_alloc(c, reinterpret_cast<void **>(&s.partials),
-                           sizeof(svt::BlockPartial) * c->max_grid + 2 * sizeof(uint32_t) * 64);
-        if (st == SVT_OK) {
-            s.counters = reinterpret_cast<uint32_t *>(s.partials + c->max_grid);
-            if (hipMemset(s.counters, 0, 2 * sizeof(uint32_t)) != hipSuccess)
-                st = hip_fail(hipGetLastError(), "hipMemset");
-        }
         if (st == SVT_OK &&
-            hipHostMalloc(reinterpret_cast<void **>(&s.summary), sizeof(svt::SummaryDev),
+            hipHostMalloc(reinterpret_cast<void **>(&s.partials),
+                          sizeof(svt::BlockPartial) * c->max_grid,
                           hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
             st = hip_fail(hipGetLastError(), "hipHostMalloc");
         if (st != SVT_OK) {
@@ -226,7 +218,7 @@ svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes)
             *out = nullptr;
             return st;
         }
-        memset(s.summary, 0, sizeof(svt::SummaryDev));
+        memset(s.partials, 0, sizeof(svt::BlockPartial) * c->max_grid);
     }
     *out = c;
     return SVT_OK;
@@ -242,8 +234,7 @@ svt_status svt_destroy(svt_ctx *c)
         if (s.busy && s.ev_end) (void)hipEventSynchronize(s.ev_end);
         if (s.ev_start) (void)hipEventDestroy(s.ev_start);
         if (s.ev_end) (void)hipEventDestroy(s.ev_end);
-        if (s.partials) (void)hipFree(s.partials);
-        if (s.summary) (void)hipHostFree(s.summary);
+        if (s.partials) (void)hipHostFree(s.partials);
         if (s.stage.ptr) (void)hipFree(s.stage.ptr);
         if (s.scan.ptr) (void)hipFree(s.scan.ptr);
     }
@@ -452,13 +443,10 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     if (grid < 1) grid = 1;
     a.events_per_chunk = epc;
     a.schedule = c->tuning.schedule;
-    a.partials = s.partials;
-    a.done = s.counters;
-    a.work = s.counters + 1;
-    a.summary = static_cast<svt::SummaryDev *>(const_cast<void *>(device_view(s.summary, SVT_MEM_MAPPED)));
+    a.partials = static_cast<svt::BlockPartial *>(
+        const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
     a.seq = (uint32_t)c->next_ticket;
-    s.summary->seq = 0;
-    s.summary->status = SVT_E_DEVICE;
+    s.grid = (int)grid;
 
     hipError_t e = svt::launch_fit(a, (int)grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
     if (e != hipSuccess) return hip_fail(e, "fit kernel launch");
@@ -507,15 +495,33 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
             std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
     }
-    const svt::SummaryDev d = *s.summary;
-    svt_status status = (d.seq == (uint32_t)t) ? (svt_status)d.status : SVT_E_DEVICE;
+    // reduce the blocks' partial sums
+    uint64_t comb = 0, pass = 0;
+    uint32_t trk = 0, er = 0xFFFFFFFFu, ee = 0xFFFFFFFFu;
+    bool complete = true;
+    for (int b = 0; b < s.grid; ++b) {
+        const svt::BlockPartial p = s.partials[b];
+        complete = complete && p.seq == (uint32_t)t;
+        comb += p.comb;
+        pass += p.pass;
+        trk += p.tracks;
+        er = p.err_road < er ? p.err_road : er;
+        ee = p.err_event < ee ? p.err_event : ee;
+    }
+    svt_status status = SVT_OK;
+    if (!complete) {
+        g_last_error = "fit kernel did not report every block";
+        status = SVT_E_DEVICE;
+    } else if (er != 0xFFFFFFFFu || ee != 0xFFFFFFFFu) {
+        status = SVT_E_RANGE;
+    }
     if (out) {
         memset(out, 0, sizeof *out);
-        out->total_comb = d.total_comb;
-        out->total_pass = d.total_pass;
-        out->total_tracks = d.total_tracks;
-        out->err_road = d.err_road;
-        out->err_event = d.err_event;
+        out->total_comb = (int64_t)comb;
+        out->total_pass = (int64_t)pass;
+        out->total_tracks = (int32_t)trk;
+        out->err_road = er == 0xFFFFFFFFu ? -1 : (int32_t)er;
+        out->err_event = ee == 0xFFFFFFFFu ? -1 : (int32_t)ee;
         out->status = status;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, s.ev_start, s.ev_end) == hipSuccess)

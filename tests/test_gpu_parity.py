@@ -146,7 +146,8 @@ def test_empty_inputs(ctx, oracle_lib):
 
 
 @pytest.mark.parametrize("tuning", [dict(events_per_chunk=1), dict(events_per_chunk=7),
-                                    dict(events_per_chunk=256), dict(blocks_per_cu=1),
+                                    dict(events_per_chunk=256), dict(blocks_per_cu=1, schedule=1),
+                                    dict(blocks_per_cu=3, schedule=1),
                                     dict(blocks_per_cu=8, schedule=2),
                                     dict(events_per_chunk=3, schedule=2)])
 def test_launch_shapes_same_bits(ctx, oracle_lib, tuning):
@@ -156,7 +157,7 @@ def test_launch_shapes_same_bits(ctx, oracle_lib, tuning):
         svt.check(svt.svt_set_tuning(ctx, **tuning))
         check_case(ctx, oracle_lib, batch, consts, f"{tuning}: ")
     finally:
-        svt.check(svt.svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=2, schedule=1))
+        svt.check(svt.svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=3, schedule=1))
 
 
 @pytest.mark.parametrize("kinds", [(0, 0), (1, 1), (2, 2), (1, 3), (3, 1), (2, 3)])
