@@ -193,6 +193,67 @@ typedef struct {
 } svt_device_info;
 svt_status svt_get_device_info(svt_ctx *ctx, svt_device_info *info);
 
+/* ------------------------------------------------------------------------
+ * Float shadow of the fit, for calibrating the constants before they are
+ * quantized.  The same linearized fit (Sec. 2: each row a scalar product of
+ * per-sector constants with the inputs plus an offset) evaluated in fp32 on
+ * unquantized input words, with every sum over tracks accumulated in fp64 in
+ * a fixed order (bit-reproducible).  Loss of N tracks:
+ *   L = (1/N) sum_t [ sum_{k<3} w_k (y_k - tau_k)^2 + sum_{k>=3} y_k^2 ]
+ *       + lambda sum_s || C_s C_s^T - I ||_F^2       (C_s: rows 3..5 of sector s)
+ * All pointers below are device memory; calls are asynchronous on hip_stream
+ * (NULL = the context's stream).  Shadow calls on one context must not run
+ * concurrently on different streams (they share the context's scratch).
+ * Errors: SVT_E_INVAL (NULL, counts out of range), SVT_E_NOMEM, SVT_E_DEVICE.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_tracks, n_sectors;     /* n_sectors in 1..256                      */
+    const float *x;                  /* [n_tracks][6] input words                */
+    const float *tau;                /* [n_tracks][3] truth of rows 0..2         */
+    const int32_t *sector_offsets;   /* [n_sectors+1] tracks of sector s are
+                                        [off[s], off[s+1]); off[0] = 0,
+                                        nondecreasing, last = n_tracks (other
+                                        values are clamped, never read out of
+                                        bounds, and give unspecified results)   */
+    float w[3];                      /* weights of the row 0..2 residuals        */
+    int32_t pad_;
+} svt_shadow_tracks;
+
+/* Fit rows y (optional [n_tracks][6], may be NULL) and the data term of L
+ * (double, written to loss[0]).  coef [n_sectors][6][6], offset [n_sectors][6]. */
+svt_status svt_shadow_forward(svt_ctx *ctx, const svt_shadow_tracks *tracks, const float *coef,
+                              const float *offset, float *y, double *loss, void *hip_stream);
+
+/* scale * dL_data/dcoef and scale * dL_data/doffset (hand-written backward:
+ * (2/N) sum_t w_k r_tk x_tj and (2/N) sum_t w_k r_tk), written in fp64, and
+ * also in fp32 where the _f32 pointers are not NULL.  scale is a device
+ * double (the incoming gradient of the loss), NULL meaning 1. */
+svt_status svt_shadow_backward(svt_ctx *ctx, const svt_shadow_tracks *tracks, const float *coef,
+                               const float *offset, const double *scale, double *grad_coef,
+                               double *grad_offset, float *grad_coef_f32,
+                               float *grad_offset_f32, void *hip_stream);
+
+/* value[0] = lambda sum_s ||C_s C_s^T - I||^2; its gradient 4 lambda (C C^T - I) C
+ * is ADDED to grad_coef (fp64; rows 3..5) and the sum copied to grad_coef_f32
+ * when not NULL. */
+svt_status svt_shadow_penalty(svt_ctx *ctx, int32_t n_sectors, const float *coef, double lambda,
+                              double *value, double *grad_coef, float *grad_coef_f32,
+                              void *hip_stream);
+
+/* One Adam step on n fp32 parameters from fp64 gradients (step counts from 1). */
+svt_status svt_shadow_adam(svt_ctx *ctx, int32_t n, float *param, const double *grad, float *m,
+                           float *v, float lr, float beta1, float beta2, float eps, int32_t step,
+                           void *hip_stream);
+
+/* Integer constants from fp32 ones, per sector: the largest shift S in
+ * [-30, 30] such that every |rint(A 2^S)| < max_abs and every row satisfies
+ * the svt_load_constants bound; rint rounds half to even.  Writes coef_int
+ * [S][6][6], offset_int [S][6], shift [S]; sets *status (device int) to 1 if
+ * a sector has no valid shift (its shift is then INT32_MIN). */
+svt_status svt_requantize(svt_ctx *ctx, int32_t n_sectors, const float *coef, const float *offset,
+                          int32_t max_abs, int32_t *coef_int, int32_t *offset_int, int32_t *shift,
+                          int32_t *status, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@
 
 #include "svt.h"
 #include "svt_internal.h"
+#include "svt_shadow.h"
 
 namespace {
 
@@ -71,6 +72,7 @@ struct svt_ctx {
     // requests
     Slot slots[kSlots];
     svt_ticket next_ticket = 1;
+    DevBuf shadow_scratch;                   // float-shadow partial sums
     svt_tuning tuning{0, 3, 1, 0};  // auto chunk, 3 blocks/CU, cyclic
 };
 
@@ -239,6 +241,7 @@ svt_status svt_destroy(svt_ctx *c)
         if (s.scan.ptr) (void)hipFree(s.scan.ptr);
     }
     if (c->coef) (void)hipFree(c->coef);
+    if (c->shadow_scratch.ptr) (void)hipFree(c->shadow_scratch.ptr);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return SVT_OK;
@@ -532,6 +535,90 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     s.busy = false;
     s.ticket = -1;
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// float shadow
+// ---------------------------------------------------------------------------
+static bool shadow_ok(const svt_shadow_tracks *t)
+{
+    return t && t->n_tracks >= 0 && t->n_sectors >= 1 && t->n_sectors <= 256 &&
+           t->sector_offsets && (t->n_tracks == 0 || (t->x && t->tau));
+}
+
+svt_status svt_shadow_forward(svt_ctx *c, const svt_shadow_tracks *t, const float *coef,
+                              const float *offset, float *y, double *loss, void *hip_stream)
+{
+    if (c == nullptr || !shadow_ok(t) || coef == nullptr || offset == nullptr || loss == nullptr)
+        return SVT_E_INVAL;
+    DeviceGuard g(c->device);
+    svt_status r = ensure(c, c->shadow_scratch, svt::shadow_scratch_bytes(t->n_tracks, t->n_sectors));
+    if (r != SVT_OK) return r;
+    svt::ShadowCall sc{t->x, t->tau, t->sector_offsets, t->n_tracks, t->n_sectors,
+                       {t->w[0], t->w[1], t->w[2]}, coef, offset, y, loss,
+                       nullptr, nullptr, nullptr, nullptr};
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipError_t e = svt::launch_shadow_forward(sc, static_cast<double *>(c->shadow_scratch.ptr), st);
+    return e == hipSuccess ? SVT_OK : hip_fail(e, "shadow forward launch");
+}
+
+svt_status svt_shadow_backward(svt_ctx *c, const svt_shadow_tracks *t, const float *coef,
+                               const float *offset, const double *scale, double *grad_coef,
+                               double *grad_offset, float *grad_coef_f32, float *grad_offset_f32,
+                               void *hip_stream)
+{
+    if (c == nullptr || !shadow_ok(t) || coef == nullptr || offset == nullptr ||
+        grad_coef == nullptr || grad_offset == nullptr)
+        return SVT_E_INVAL;
+    DeviceGuard g(c->device);
+    svt_status r = ensure(c, c->shadow_scratch, svt::shadow_scratch_bytes(t->n_tracks, t->n_sectors));
+    if (r != SVT_OK) return r;
+    svt::ShadowCall sc{t->x, t->tau, t->sector_offsets, t->n_tracks, t->n_sectors,
+                       {t->w[0], t->w[1], t->w[2]}, coef, offset, nullptr, nullptr,
+                       grad_coef, grad_offset, grad_coef_f32, grad_offset_f32};
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipError_t e = svt::launch_shadow_backward(sc, scale, static_cast<double *>(c->shadow_scratch.ptr), st);
+    return e == hipSuccess ? SVT_OK : hip_fail(e, "shadow backward launch");
+}
+
+svt_status svt_shadow_penalty(svt_ctx *c, int32_t n_sectors, const float *coef, double lambda,
+                              double *value, double *grad_coef, float *grad_coef_f32,
+                              void *hip_stream)
+{
+    if (c == nullptr || n_sectors < 1 || n_sectors > 256 || coef == nullptr || value == nullptr ||
+        grad_coef == nullptr)
+        return SVT_E_INVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipError_t e = svt::launch_shadow_penalty(coef, n_sectors, lambda, value, grad_coef, grad_coef_f32, st);
+    return e == hipSuccess ? SVT_OK : hip_fail(e, "shadow penalty launch");
+}
+
+svt_status svt_shadow_adam(svt_ctx *c, int32_t n, float *param, const double *grad, float *m,
+                           float *v, float lr, float beta1, float beta2, float eps, int32_t step,
+                           void *hip_stream)
+{
+    if (c == nullptr || n < 0 || step < 1 || (n > 0 && (!param || !grad || !m || !v)))
+        return SVT_E_INVAL;
+    if (n == 0) return SVT_OK;
+    DeviceGuard g(c->device);
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipError_t e = svt::launch_adam(n, param, grad, m, v, lr, beta1, beta2, eps, step, st);
+    return e == hipSuccess ? SVT_OK : hip_fail(e, "adam launch");
+}
+
+svt_status svt_requantize(svt_ctx *c, int32_t n_sectors, const float *coef, const float *offset,
+                          int32_t max_abs, int32_t *coef_int, int32_t *offset_int, int32_t *shift,
+                          int32_t *status, void *hip_stream)
+{
+    if (c == nullptr || n_sectors < 1 || n_sectors > 256 || !coef || !offset || !coef_int ||
+        !offset_int || !shift || !status || max_abs < 1)
+        return SVT_E_INVAL;
+    DeviceGuard g(c->device);
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipError_t e = svt::launch_requantize(coef, offset, n_sectors, max_abs, coef_int, offset_int,
+                                          shift, status, st);
+    return e == hipSuccess ? SVT_OK : hip_fail(e, "requantize launch");
 }
 
 }  // extern "C"

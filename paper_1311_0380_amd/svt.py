@@ -57,6 +57,12 @@ class svt_device_info(ctypes.Structure):
                 ("used_bytes", ctypes.c_int64), ("arch", ctypes.c_char * 32)]
 
 
+class svt_shadow_tracks(ctypes.Structure):
+    _fields_ = [("n_tracks", ctypes.c_int32), ("n_sectors", ctypes.c_int32),
+                ("x", P), ("tau", P), ("sector_offsets", P),
+                ("w", ctypes.c_float * 3), ("pad_", ctypes.c_int32)]
+
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = {
     "svt_create": (ctypes.c_int32, [ctypes.POINTER(P), ctypes.c_int32, ctypes.c_size_t]),
@@ -72,6 +78,14 @@ SIGNATURES = {
     "svt_set_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
     "svt_get_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
     "svt_get_device_info": (ctypes.c_int32, [P, ctypes.POINTER(svt_device_info)]),
+    "svt_shadow_forward": (ctypes.c_int32, [P, ctypes.POINTER(svt_shadow_tracks), P, P, P, P, P]),
+    "svt_shadow_backward": (ctypes.c_int32, [P, ctypes.POINTER(svt_shadow_tracks), P, P, P, P, P,
+                                             P, P, P]),
+    "svt_shadow_penalty": (ctypes.c_int32, [P, ctypes.c_int32, P, ctypes.c_double, P, P, P, P]),
+    "svt_shadow_adam": (ctypes.c_int32, [P, ctypes.c_int32, P, P, P, P, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_int32, P]),
+    "svt_requantize": (ctypes.c_int32, [P, ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, P, P]),
 }
 
 

@@ -359,67 +359,115 @@ def log_uniform_mean(max_events: int = 3000) -> float:
 @dataclasses.dataclass
 class HelixGeometry:
     radii_cm: tuple = (3.0, 5.0, 7.0, 10.0)   # silicon layers
-    xft_radius_cm: float = 100.0              # XFT (drift chamber) reference radius
-    n_sectors: int = 72                       # phi sectors of 5 degrees
-    pitch_um: float = 4.0                     # silicon word unit
+    xft_radius_cm: float = 100.0              # XFT reference radius; Rmax = this radius
+    n_sectors: int = 72                       # phi sectors of 5 degrees (sector set at layer 2)
+    pitch_um: float = 4.0                     # silicon word unit (local arc length)
     word_center: float = 2048.0
     sigma_um: float = 10.0                    # silicon hit smearing
     d0_sigma_um: float = 50.0
-    xft_phi_unit_urad: float = 40.0           # XFT phi word unit
-    xft_curv_unit: float = 1.0 / 2048.0       # XFT curvature word unit (of 1/Rmax)
-    xft_sigma_words: float = 1.0
+    xft_phi_unit_urad: float = 300.0          # XFT phi word unit (local angle at Rmax)
+    xft_curv_words: float = 2000.0            # words per unit of curvature * Rmax
+    xft_sigma_words: float = 1.0              # XFT word smearing
+    # parameter-word units of the truth (d0 [um], local phi0 [urad], curvature * Rmax * 1e3)
+    truth_scale: tuple = (1.0, 1.0, 1000.0)
 
 
 @dataclasses.dataclass
 class HelixTracks:
-    x: np.ndarray        # float64 [N, 6] unquantized input words
-    xq: np.ndarray       # int16 [N, 6] quantized words (those in range)
-    truth: np.ndarray    # float64 [N, 3] (d0 [um], phi-local [urad], curvature [1/Rmax])
-    sector: np.ndarray   # int32 [N]
-    kept: np.ndarray     # bool [N] all six words inside [0, 4096)
+    x: np.ndarray              # float64 [N, 6] unquantized input words
+    xq: np.ndarray             # int16 [N, 6] words rounded to integers (clipped to [0, 4095])
+    truth: np.ndarray          # float64 [N, 3] parameter words (d0 um, phi0 urad, 1e3 c Rmax)
+    sector: np.ndarray         # int32 [N] ascending (tracks grouped by sector)
+    sector_offsets: np.ndarray # int32 [n_sectors + 1] tracks of sector s: [off[s], off[s+1])
+    kept: np.ndarray           # bool [N] all six rounded words inside [0, 4096)
+    dropped: int               # generated tracks removed because a word left [0, 4096)
 
 
 def helix_tracks(n: int, seed: int = 4, geom: HelixGeometry = None) -> HelixTracks:
-    """Synthetic charged tracks in the transverse plane.
+    """Charged tracks in the transverse plane for the calibration workload.
 
-    d0 ~ N(0, 50 um), phi ~ U[0, 2 pi), curvature ~ U[-1, 1] / Rmax with
-    Rmax the XFT radius; silicon hits smeared with N(0, 10 um).  Each input
-    word is a local coordinate inside the track's 5 degree phi sector:
-    silicon words are the arc position (um) / pitch + 2048 at each layer
-    radius, the XFT words are the curvature and the local phi at the XFT
-    radius.  Words outside [0, 4096) drop the track (reported by `kept`).
+    d0 ~ N(0, 50 um), phi0 ~ U[0, 2 pi), curvature ~ U[-1, 1] / Rmax with Rmax
+    the XFT radius; silicon hits smeared with N(0, 10 um).  Each input word
+    is a local coordinate inside the track's 5 degree phi sector (the sector
+    is the one the track crosses at layer 2): silicon words are the arc
+    position / pitch + 2048 at each layer radius; the XFT words are the
+    curvature and the local phi at the XFT radius.  The circle / cylinder
+    intersection is exact.  Tracks with a word outside [0, 4096) after
+    rounding are dropped (and counted); the rest are returned grouped by
+    sector.
     """
     g = geom or HelixGeometry()
     rng = np.random.default_rng(seed)
-    d0 = rng.normal(0.0, g.d0_sigma_um, n) * 1e-4                 # cm
-    phi0 = rng.uniform(0.0, 2.0 * np.pi, n)
-    rmax = g.xft_radius_cm
-    curv = rng.uniform(-1.0, 1.0, n) / rmax                          # 1/cm (signed 1/R)
+    want = n
+    xs, ts, ss = [], [], []
+    dropped = 0
     width = 2.0 * np.pi / g.n_sectors
+    rmax = g.xft_radius_cm
+    while want > 0:
+        m = int(want * 1.05) + 16
+        d0 = rng.normal(0.0, g.d0_sigma_um, m) * 1e-4                 # cm
+        phi0 = rng.uniform(0.0, 2.0 * np.pi, m)
+        curv = rng.uniform(-1.0, 1.0, m) / rmax                         # signed 1/R in 1/cm
 
-    def phi_at(r):
-        # exact helix in the transverse plane for a track with impact
-        # parameter d0, direction phi0 and curvature curv, crossing radius r
-        # (small-curvature form of the circle/cylinder intersection)
-        arg = (curv * r) / 2.0 + (d0 / r) * (1.0 + curv * d0 / 2.0)
-        return phi0 + np.arcsin(np.clip(arg, -1.0, 1.0))
+        def phi_at(r):
+            # azimuth where a circle of curvature curv, impact parameter d0 and
+            # direction phi0 at closest approach crosses radius r
+            arg = (curv * r) / 2.0 + (d0 / r) * (1.0 + curv * d0 / 2.0) / (1.0 + curv * d0)
+            return phi0 + np.arcsin(np.clip(arg, -1.0, 1.0))
 
-    r2 = g.radii_cm[2]
-    sector = np.floor(np.mod(phi_at(r2), 2.0 * np.pi) / width).astype(np.int64) % g.n_sectors
-    sec_center = (sector + 0.5) * width
-    x = np.zeros((n, 6))
-    for layer, r in enumerate(g.radii_cm):
-        dphi = np.angle(np.exp(1j * (phi_at(r) - sec_center)))
-        arc_um = dphi * r * 1e4 + rng.normal(0.0, g.sigma_um, n)
-        x[:, layer] = arc_um / g.pitch_um / 60.0 + g.word_center
-    x[:, 4] = curv * rmax / g.xft_curv_unit / 2.0 + g.word_center \
-        + rng.normal(0.0, g.xft_sigma_words, n)
-    dphi_x = np.angle(np.exp(1j * (phi_at(min(rmax * 0.99, rmax)) - sec_center)))
-    x[:, 5] = dphi_x * 1e6 / g.xft_phi_unit_urad / 10.0 + g.word_center \
-        + rng.normal(0.0, g.xft_sigma_words, n)
+        sector = np.floor(np.mod(phi_at(g.radii_cm[2]), 2.0 * np.pi) / width).astype(np.int64)
+        sector = np.minimum(sector, g.n_sectors - 1)
+        center = (sector + 0.5) * width
+        x = np.zeros((m, 6))
+        for layer, r in enumerate(g.radii_cm):
+            dphi = np.angle(np.exp(1j * (phi_at(r) - center)))
+            arc_um = dphi * r * 1e4 + rng.normal(0.0, g.sigma_um, m)
+            x[:, layer] = arc_um / g.pitch_um + g.word_center
+        x[:, 4] = curv * rmax * g.xft_curv_words + g.word_center \
+            + rng.normal(0.0, g.xft_sigma_words, m)
+        dphi_x = np.angle(np.exp(1j * (phi_at(rmax) - center)))
+        x[:, 5] = dphi_x * 1e6 / g.xft_phi_unit_urad + g.word_center \
+            + rng.normal(0.0, g.xft_sigma_words, m)
+        truth = np.stack([d0 * 1e4 * g.truth_scale[0],
+                          np.angle(np.exp(1j * (phi0 - center))) * 1e6 * g.truth_scale[1],
+                          curv * rmax * g.truth_scale[2]], axis=1)
+        ok = np.all((np.rint(x) >= 0) & (np.rint(x) < HIT_RANGE), axis=1)
+        dropped += int((~ok).sum())
+        take = np.nonzero(ok)[0][:want]
+        xs.append(x[take]); ts.append(truth[take]); ss.append(sector[take])
+        want -= take.size
+    x = np.concatenate(xs); truth = np.concatenate(ts); sector = np.concatenate(ss)
+    order = np.argsort(sector, kind="stable")
+    x, truth, sector = x[order], truth[order], sector[order]
+    off = np.zeros(g.n_sectors + 1, np.int64)
+    np.add.at(off, sector + 1, 1)
+    off = np.cumsum(off)
     xq = np.rint(x)
-    kept = np.all((xq >= 0) & (xq < HIT_RANGE), axis=1)
-    truth = np.stack([d0 * 1e4, np.angle(np.exp(1j * (phi0 - sec_center))) * 1e6,
-                      curv * rmax], axis=1)
     return HelixTracks(x=x, xq=np.clip(xq, 0, HIT_RANGE - 1).astype(np.int16), truth=truth,
-                       sector=sector.astype(np.int32), kept=kept)
+                       sector=sector.astype(np.int32), sector_offsets=off.astype(np.int32),
+                       kept=np.ones(x.shape[0], bool), dropped=dropped)
+
+
+def pilot_constants(h: HelixTracks, frac: float = 0.02, seed: int = 7):
+    """Starting constants for calibration from a small pilot sample (the role
+    nominal geometry constants play before a calibration): per sector, least
+    squares of the truth on the words for rows 0..2, and the three
+    smallest-variance directions of the words (unit rows, centred) for rows
+    3..5.  float32 [S,6,6], [S,6]."""
+    rng = np.random.default_rng(seed)
+    n_s = h.sector_offsets.shape[0] - 1
+    coef = np.zeros((n_s, 6, 6))
+    off = np.zeros((n_s, 6))
+    for s in range(n_s):
+        a, e = int(h.sector_offsets[s]), int(h.sector_offsets[s + 1])
+        take = rng.choice(np.arange(a, e), size=max(32, int((e - a) * frac)), replace=False)
+        X = h.x[take]
+        Xa = np.hstack([X, np.ones((X.shape[0], 1))])
+        sol, *_ = np.linalg.lstsq(Xa, h.truth[take], rcond=None)
+        coef[s, :3] = sol[:6].T
+        off[s, :3] = sol[6]
+        mu = X.mean(axis=0)
+        _, vec = np.linalg.eigh(np.cov((X - mu).T))
+        coef[s, 3:] = vec[:, :3].T
+        off[s, 3:] = -coef[s, 3:] @ mu
+    return coef.astype(np.float32), off.astype(np.float32)

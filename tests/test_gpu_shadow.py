@@ -1,0 +1,137 @@
+"""GPU float shadow: fp32 kernels against the FP64 oracle within the stated
+tolerance, the hand-written backward against the FP64 gradient, the autograd
+wrapper, requantization bit for bit, calibration, and rescoring on the
+integer path."""
+import numpy as np
+import pytest
+
+from oracle import shadow as osh
+from paper_1311_0380_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+W = (1.0 / 400.0, 1.0 / 1.0e4, 1.0)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1311_0380_amd import shadow, svt
+    h = synth.helix_tracks(120000, seed=44)
+    coef, off = synth.pilot_constants(h)
+    rng = np.random.default_rng(5)
+    # a point away from the optimum: residuals are large, as early in a calibration
+    coef = (coef * (1 + rng.normal(0, 0.02, coef.shape))).astype(np.float32)
+    off = (off + rng.normal(0, 5.0, off.shape)).astype(np.float32)
+    handle = svt.svt_create(0, 0)
+    tr = shadow.ShadowTracks.from_helix(h, W)
+    yield dict(h=h, coef=coef, off=off, handle=handle, tracks=tr, torch=torch, shadow=shadow)
+    svt.svt_destroy(handle)
+
+
+def dev(env, a):
+    return env["torch"].tensor(a, device="cuda")
+
+
+def test_forward_rows_and_loss(env):
+    h, coef, off = env["h"], env["coef"], env["off"]
+    loss, y = env["shadow"].forward(env["handle"], env["tracks"], dev(env, coef), dev(env, off),
+                                    want_y=True)
+    y = y.cpu().numpy().astype(np.float64)
+    xs = h.x.astype(np.float32)
+    want_loss, want_y = osh.data_loss(coef, off, xs, h.truth.astype(np.float32),
+                                      h.sector_offsets, W)
+    # |y - y*| <= 1e-6 * max(|y*|, S), S = sum_j |A_kj x_j| + |b_k|
+    s = np.repeat(np.arange(len(h.sector_offsets) - 1), np.diff(h.sector_offsets))
+    S = np.einsum("tkj,tj->tk", np.abs(coef.astype(np.float64))[s], np.abs(xs.astype(np.float64))) \
+        + np.abs(off.astype(np.float64))[s]
+    err = np.abs(y - want_y) / np.maximum(np.abs(want_y), S)
+    assert err.max() <= 1e-6, err.max()
+    assert abs(loss.item() - want_loss) <= 1e-6 * want_loss
+
+
+def test_backward_matches_fp64_gradient(env):
+    h, coef, off = env["h"], env["coef"], env["off"]
+    g64, o64, g32, o32 = env["shadow"].backward(env["handle"], env["tracks"], dev(env, coef),
+                                                dev(env, off))
+    gA, gb = osh.data_grad(coef, off, h.x.astype(np.float32), h.truth.astype(np.float32),
+                           h.sector_offsets, W)
+    assert np.abs(g64.cpu().numpy() - gA).max() <= 1e-6 * np.abs(gA).max()
+    assert np.abs(o64.cpu().numpy() - gb).max() <= 1e-6 * np.abs(gb).max()
+    assert np.array_equal(g32.cpu().numpy(), g64.cpu().numpy().astype(np.float32))
+    # bit-reproducible
+    g64b, o64b, _, _ = env["shadow"].backward(env["handle"], env["tracks"], dev(env, coef),
+                                              dev(env, off))
+    assert env["torch"].equal(g64, g64b) and env["torch"].equal(o64, o64b)
+
+
+def test_penalty(env):
+    torch = env["torch"]
+    coef = env["coef"]
+    lam = 7.0
+    g = torch.zeros((coef.shape[0], 6, 6), dtype=torch.float64, device="cuda")
+    val = env["shadow"].penalty(env["handle"], dev(env, coef), lam, g)
+    want_v, want_g = osh.penalty(coef, lam)
+    assert abs(val.item() - want_v) <= 1e-9 * max(1.0, want_v)
+    assert np.abs(g.cpu().numpy() - want_g).max() <= 1e-9 * max(1.0, np.abs(want_g).max())
+
+
+def test_autograd_function_and_finite_differences(env):
+    torch = env["torch"]
+    h, coef, off = env["h"], env["coef"], env["off"]
+    A = dev(env, coef).requires_grad_(True)
+    b = dev(env, off).requires_grad_(True)
+    L = env["shadow"].SVTShadowFit.apply(A, b, env["handle"], env["tracks"]) * 3.0
+    L.backward()
+    gA, gb = osh.data_grad(coef, off, h.x.astype(np.float32), h.truth.astype(np.float32),
+                           h.sector_offsets, W)
+    assert np.abs(A.grad.cpu().numpy() - 3.0 * gA).max() <= 2e-6 * np.abs(3.0 * gA).max()
+    assert np.abs(b.grad.cpu().numpy() - 3.0 * gb).max() <= 2e-6 * np.abs(3.0 * gb).max()
+    # the FP64 gradient it matches is itself checked by central differences
+    for idx in [(3, 0, 0), (10, 4, 2)]:
+        fd = osh.finite_difference(coef, off, h.x.astype(np.float32), h.truth.astype(np.float32),
+                                   h.sector_offsets, W, 0.0, idx, h=1e-3)
+        assert abs(fd - gA[idx]) <= 1e-6 * max(1.0, abs(gA[idx]))
+
+
+def test_requantize_bit_exact(env):
+    coef, off = env["coef"], env["off"]
+    ci, oi, sh, status = env["shadow"].requantize(env["handle"], dev(env, coef), dev(env, off))
+    wci, woi, wsh = osh.requantize(coef, off)
+    assert status.item() == 0
+    assert np.array_equal(sh.cpu().numpy(), wsh)
+    assert np.array_equal(ci.cpu().numpy(), wci)
+    assert np.array_equal(oi.cpu().numpy(), woi)
+
+
+def test_calibration_reduces_loss_and_rescore(env, oracle_lib):
+    torch = env["torch"]
+    from paper_1311_0380_amd import svt
+    h = env["h"]
+    coef, off = synth.pilot_constants(h)
+    res = env["shadow"].calibrate(env["handle"], env["tracks"], dev(env, coef), dev(env, off),
+                                  steps=60, lr=2e-3, lam=10.0, record_every=20)
+    losses = [l for _, l, _ in res.history]
+    start, _ = osh.data_loss(coef, off, h.x.astype(np.float32), h.truth.astype(np.float32),
+                             h.sector_offsets, W)
+    assert losses[-1] < start
+    # requantize and rescore the quantized words on the integer path: one
+    # road per track with one hit per layer
+    ci, oi, sh, status = env["shadow"].requantize(env["handle"], res.coef, res.offset)
+    assert status.item() == 0
+    ci, oi = ci.cpu().numpy(), oi.cpu().numpy()
+    n = 20000
+    xq = h.xq[:n].astype(np.int16)
+    b = synth.Batch(road_offsets=np.arange(n + 1, dtype=np.int32),
+                    sector=h.sector[:n].astype(np.uint8),
+                    nhits=np.ones((n, 4), np.uint8),
+                    hit_offsets=(np.arange(n + 1) * 4).astype(np.int32),
+                    hits=xq[:, :4].reshape(-1).copy(), xft=xq[:, 4:6].copy())
+    cut = (1 << 48) - 1
+    svt.check(svt.svt_load_constants(env["handle"], ci, oi, cut))
+    from tests.gpu_helpers import assert_equal_results, lib_fit
+    st, summ, got = lib_fit(env["handle"], b)
+    assert st == 0
+    rc, want, _ = oracle_lib.fit_batch(b, synth.Constants(ci, oi, cut))
+    assert rc == 0
+    assert_equal_results(got, want)
