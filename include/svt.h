@@ -194,6 +194,33 @@ typedef struct {
 svt_status svt_get_device_info(svt_ctx *ctx, svt_device_info *info);
 
 /* ------------------------------------------------------------------------
+ * Plans: uneven batches fitted by one persistent, graph-captured launch.
+ * A plan owns device buffers for a batch of up to max_events / max_roads /
+ * max_hits and a captured graph [copy of the batch sizes from pinned host
+ * memory -> fit kernel over a fixed persistent grid reading those sizes], so
+ * one graph replays any batch within capacity.  The launch shape comes from
+ * tuning (NULL or 0 fields: the context's).  Constants are captured: after
+ * svt_load_constants the plan must be recreated (svt_plan_fit returns
+ * SVT_E_STATE).  One request per plan may be in flight.
+ * ------------------------------------------------------------------------ */
+svt_status svt_plan_create(svt_ctx *ctx, int32_t max_events, int32_t max_roads, int32_t max_hits,
+                           const svt_tuning *tuning, svt_plan **out);
+svt_status svt_plan_destroy(svt_plan *plan);
+
+/* Device views of the plan's own input and result buffers (capacities in the
+ * counts).  A batch whose pointers are these buffers is fitted in place, and
+ * results requested into these buffers are not copied. */
+svt_status svt_plan_buffers(svt_plan *plan, svt_event_batch *in, svt_results *out);
+
+/* Like svt_fit_events (same contracts and errors; completion through
+ * svt_result on the plan's context), replaying the plan's graph.  Inputs
+ * and results of any memory kind are copied into / out of the plan's
+ * buffers unless they are those buffers.  Batches above capacity:
+ * SVT_E_INVAL.  comb_offsets, if requested, must be device memory. */
+svt_status svt_plan_fit(svt_plan *plan, const svt_event_batch *batch, const svt_results *res,
+                        void *hip_stream, svt_ticket *ticket);
+
+/* ------------------------------------------------------------------------
  * Float shadow of the fit, for calibrating the constants before they are
  * quantized.  The same linearized fit (Sec. 2: each row a scalar product of
  * per-sector constants with the inputs plus an offset) evaluated in fp32 on

@@ -473,10 +473,12 @@ fit_kernel(FitArgs a)
     const int tid = threadIdx.x;
 
     int32_t n_events = a.n_events, n_roads = a.n_roads, n_hits = a.n_hits;
+    uint32_t seq = a.seq;
     if (a.sizes != nullptr) {
         n_events = a.sizes->n_events;
         n_roads = a.sizes->n_roads;
         n_hits = a.sizes->n_hits;
+        seq = a.sizes->seq;
     }
     const int32_t n_sectors = a.n_sectors;
     double *s_cd = reinterpret_cast<double *>(s_dyn);
@@ -554,7 +556,7 @@ fit_kernel(FitArgs a)
             p.err_road = min(p.err_road, s_part[w].err_road);
             p.err_event = min(p.err_event, s_part[w].err_event);
         }
-        p.seq = a.seq;
+        p.seq = seq;
         a.partials[blockIdx.x] = p;
     }
 }
@@ -623,16 +625,15 @@ __global__ void zero_i64(int64_t *p)
 
 }  // namespace
 
+hipError_t prepare_fit()
+{
+    const int max_dyn = 256 * kCstBytesPerSector;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
+}
+
 hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream)
 {
-    static bool attr_done = false;
-    if (!attr_done) {
-        const int max_dyn = 256 * kCstBytesPerSector;
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
     hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), dyn_lds, stream, a);
     return hipGetLastError();
 }

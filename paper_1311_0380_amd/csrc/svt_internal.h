@@ -27,7 +27,8 @@ constexpr int kCstIntPB = 58;     // int32 index of the parameter offsets
 
 // Sizes of a batch when they are read from device memory (graph replay).
 struct Sizes {
-    int32_t n_events, n_roads, n_hits, pad;
+    int32_t n_events, n_roads, n_hits;
+    uint32_t seq;   // request sequence number (graph replays)
 };
 
 // Partial sums of one block, written by the block into host-mapped memory and
@@ -74,6 +75,7 @@ struct FitArgs {
     uint32_t seq;
 };
 
+hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
 hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream);
 hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
                                int64_t *scratch, hipStream_t stream);

@@ -45,7 +45,9 @@ struct Slot {
     svt_ticket ticket = -1;
     hipEvent_t ev_start = nullptr, ev_end = nullptr;
     svt::BlockPartial *partials = nullptr;   // host-mapped [max grid]
+    svt::BlockPartial *parts = nullptr;      // partials the request in flight writes
     int grid = 0;                            // blocks of the request in flight
+    svt_plan *plan = nullptr;                // plan of the request, if any
     DevBuf stage;                            // device staging for host inputs / results
     DevBuf scan;                             // comb_offsets scratch
     svt_status host_status = SVT_OK;
@@ -73,7 +75,27 @@ struct svt_ctx {
     Slot slots[kSlots];
     svt_ticket next_ticket = 1;
     DevBuf shadow_scratch;                   // float-shadow partial sums
+    uint64_t const_gen = 0;                  // bumped by every svt_load_constants
     svt_tuning tuning{0, 3, 1, 0};  // auto chunk, 3 blocks/CU, cyclic
+};
+
+// A captured fit of any batch up to a fixed capacity (see svt_plan_create).
+struct svt_plan {
+    svt_ctx *ctx = nullptr;
+    int32_t max_events = 0, max_roads = 0, max_hits = 0;
+    void *buf = nullptr;                    // device: inputs + results at capacity
+    size_t buf_bytes = 0;
+    svt_event_batch in{};                   // device views of the input buffers
+    svt_results out{};                      // device views of the result buffers
+    svt::Sizes *sizes_dev = nullptr;        // read by the captured kernel
+    svt::Sizes *sizes_host = nullptr;       // pinned; copied by the captured graph
+    svt::BlockPartial *partials = nullptr;  // host-mapped [grid]
+    int grid = 0;
+    svt_tuning tuning{};
+    uint64_t const_gen = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool busy = false;
 };
 
 namespace {
@@ -146,14 +168,38 @@ const void *device_view(const void *p, int32_t kind)
     return d;
 }
 
-int auto_events_per_chunk(const svt_event_batch *b)
+int auto_events_per_chunk(int32_t n_events, int32_t n_roads)
 {
-    if (b->n_events <= 0) return 1;
-    const double rpe = (double)b->n_roads / (double)b->n_events;
+    if (n_events <= 0) return 1;
+    const double rpe = (double)n_roads / (double)n_events;
     int e = rpe > 0 ? (int)((double)svt::kTargetRoadsPerChunk / rpe + 0.5) : 256;
     if (e < 1) e = 1;
     if (e > svt::kMaxEventsPerChunk) e = svt::kMaxEventsPerChunk;
     return e;
+}
+
+// Call-level validation shared by the fit entry points.
+svt_status check_call(const svt_event_batch *b, const svt_results *res)
+{
+    if (!kind_ok(b->mem_kind) || !kind_ok(res->mem_kind)) return SVT_E_INVAL;
+    const int32_t ne = b->n_events, nr = b->n_roads, nh = b->n_hits;
+    if (ne < 0 || nr < 0 || nh < 0) return SVT_E_INVAL;
+    if (ne == 0 && nr != 0) return SVT_E_INVAL;
+    if (nr == 0 && nh != 0) return SVT_E_INVAL;
+    if (ne == INT32_MAX || nr == INT32_MAX) return SVT_E_INVAL;
+    if (b->road_offsets == nullptr) return SVT_E_INVAL;
+    if (nr > 0 && (b->sector == nullptr || b->nhits == nullptr || b->hit_offsets == nullptr ||
+                   b->xft == nullptr))
+        return SVT_E_INVAL;
+    if (nh > 0 && b->hits == nullptr) return SVT_E_INVAL;
+    if (nr > 0 && (res->ncomb == nullptr || res->npass == nullptr || res->best == nullptr ||
+                   res->chi2 == nullptr || res->params == nullptr || res->hit_index == nullptr))
+        return SVT_E_INVAL;
+    if (ne > 0 && res->ntracks == nullptr) return SVT_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(b->nhits) | reinterpret_cast<uintptr_t>(b->xft) |
+         reinterpret_cast<uintptr_t>(res->hit_index)) & 3u)
+        return SVT_E_INVAL;
+    return SVT_OK;
 }
 
 }  // namespace
@@ -199,6 +245,11 @@ svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes)
     c->hbm_bytes = prop.totalGlobalMem;
     snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
     c->max_grid = c->cu_count * svt::kMaxBlocksPerCu;
+    e = svt::prepare_fit();
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "fit kernel attributes");
+    }
     e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
@@ -274,6 +325,7 @@ svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef
     c->n_sectors = n_sectors;
     c->cut = chi2_cut;
     c->loaded = true;
+    ++c->const_gen;
     return SVT_OK;
 }
 
@@ -313,24 +365,9 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
                           void *hip_stream, svt_ticket *ticket)
 {
     if (c == nullptr || b == nullptr || res == nullptr || ticket == nullptr) return SVT_E_INVAL;
-    if (!kind_ok(b->mem_kind) || !kind_ok(res->mem_kind)) return SVT_E_INVAL;
+    const svt_status vs = check_call(b, res);
+    if (vs != SVT_OK) return vs;
     const int32_t ne = b->n_events, nr = b->n_roads, nh = b->n_hits;
-    if (ne < 0 || nr < 0 || nh < 0) return SVT_E_INVAL;
-    if (ne == 0 && nr != 0) return SVT_E_INVAL;
-    if (nr == 0 && nh != 0) return SVT_E_INVAL;
-    if (ne == INT32_MAX || nr == INT32_MAX) return SVT_E_INVAL;
-    if (b->road_offsets == nullptr) return SVT_E_INVAL;
-    if (nr > 0 && (b->sector == nullptr || b->nhits == nullptr || b->hit_offsets == nullptr ||
-                   b->xft == nullptr))
-        return SVT_E_INVAL;
-    if (nh > 0 && b->hits == nullptr) return SVT_E_INVAL;
-    if (nr > 0 && (res->ncomb == nullptr || res->npass == nullptr || res->best == nullptr ||
-                   res->chi2 == nullptr || res->params == nullptr || res->hit_index == nullptr))
-        return SVT_E_INVAL;
-    if (ne > 0 && res->ntracks == nullptr) return SVT_E_INVAL;
-    if ((reinterpret_cast<uintptr_t>(b->nhits) | reinterpret_cast<uintptr_t>(b->xft) |
-         reinterpret_cast<uintptr_t>(res->hit_index)) & 3u)
-        return SVT_E_INVAL;
     if (!c->loaded) return SVT_E_STATE;
 
     // a free ticket slot
@@ -439,7 +476,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     }
 
     const int epc = c->tuning.events_per_chunk > 0 ? c->tuning.events_per_chunk
-                                                   : auto_events_per_chunk(b);
+                                                   : auto_events_per_chunk(ne, nr);
     const int64_t n_chunks = ne > 0 ? ((int64_t)ne + epc - 1) / epc : 0;
     int64_t grid = (int64_t)c->cu_count * c->tuning.blocks_per_cu;
     if (grid > n_chunks) grid = n_chunks;
@@ -450,6 +487,8 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
     a.seq = (uint32_t)c->next_ticket;
     s.grid = (int)grid;
+    s.parts = s.partials;
+    s.plan = nullptr;
 
     hipError_t e = svt::launch_fit(a, (int)grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
     if (e != hipSuccess) return hip_fail(e, "fit kernel launch");
@@ -503,7 +542,7 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     uint32_t trk = 0, er = 0xFFFFFFFFu, ee = 0xFFFFFFFFu;
     bool complete = true;
     for (int b = 0; b < s.grid; ++b) {
-        const svt::BlockPartial p = s.partials[b];
+        const svt::BlockPartial p = s.parts[b];
         complete = complete && p.seq == (uint32_t)t;
         comb += p.comb;
         pass += p.pass;
@@ -532,6 +571,8 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
         else
             (void)hipGetLastError();
     }
+    if (s.plan) s.plan->busy = false;
+    s.plan = nullptr;
     s.busy = false;
     s.ticket = -1;
     return status;
@@ -619,6 +660,242 @@ svt_status svt_requantize(svt_ctx *c, int32_t n_sectors, const float *coef, cons
     hipError_t e = svt::launch_requantize(coef, offset, n_sectors, max_abs, coef_int, offset_int,
                                           shift, status, st);
     return e == hipSuccess ? SVT_OK : hip_fail(e, "requantize launch");
+}
+
+// ---------------------------------------------------------------------------
+// plans: one persistent, graph-captured fit of any batch within a capacity
+// ---------------------------------------------------------------------------
+static void plan_free(svt_plan *p)
+{
+    if (p == nullptr) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->buf) dev_free(p->ctx, p->buf, p->buf_bytes);
+    if (p->sizes_host) (void)hipHostFree(p->sizes_host);
+    if (p->partials) (void)hipHostFree(p->partials);
+    delete p;
+}
+
+svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, int32_t max_hits,
+                           const svt_tuning *tuning, svt_plan **out)
+{
+    if (c == nullptr || out == nullptr || max_events < 1 || max_roads < 0 || max_hits < 0 ||
+        max_events == INT32_MAX || max_roads == INT32_MAX)
+        return SVT_E_INVAL;
+    *out = nullptr;
+    if (!c->loaded) return SVT_E_STATE;
+    DeviceGuard g(c->device);
+    svt_plan *p = new (std::nothrow) svt_plan();
+    if (p == nullptr) return SVT_E_NOMEM;
+    p->ctx = c;
+    p->max_events = max_events;
+    p->max_roads = max_roads;
+    p->max_hits = max_hits;
+    p->tuning = c->tuning;
+    if (tuning) {
+        if (tuning->events_per_chunk < 0 || tuning->events_per_chunk > svt::kMaxEventsPerChunk ||
+            tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > svt::kMaxBlocksPerCu ||
+            tuning->schedule < 0 || tuning->schedule > 2) {
+            delete p;
+            return SVT_E_INVAL;
+        }
+        if (tuning->events_per_chunk) p->tuning.events_per_chunk = tuning->events_per_chunk;
+        if (tuning->blocks_per_cu) p->tuning.blocks_per_cu = tuning->blocks_per_cu;
+        if (tuning->schedule) p->tuning.schedule = tuning->schedule;
+    }
+    if (p->tuning.events_per_chunk == 0)
+        p->tuning.events_per_chunk = auto_events_per_chunk(max_events, max_roads);
+    p->const_gen = c->const_gen;
+
+    // buffer layout: inputs, then results, then the size descriptor
+    const size_t ne = (size_t)max_events, nr = (size_t)max_roads, nh = (size_t)max_hits;
+    size_t off = 0;
+    const size_t o_ro = off; off = align_up(off + 4 * (ne + 1), 256);
+    const size_t o_sec = off; off = align_up(off + nr, 256);
+    const size_t o_nh = off; off = align_up(off + 4 * nr, 256);
+    const size_t o_ho = off; off = align_up(off + 4 * (nr + 1), 256);
+    const size_t o_hits = off; off = align_up(off + 2 * nh, 256);
+    const size_t o_xft = off; off = align_up(off + 4 * nr, 256);
+    const size_t o_ncomb = off; off = align_up(off + 4 * nr, 256);
+    const size_t o_np = off; off = align_up(off + 4 * nr, 256);
+    const size_t o_best = off; off = align_up(off + 4 * nr, 256);
+    const size_t o_chi2 = off; off = align_up(off + 8 * nr, 256);
+    const size_t o_par = off; off = align_up(off + 12 * nr, 256);
+    const size_t o_hi = off; off = align_up(off + 4 * nr, 256);
+    const size_t o_ntr = off; off = align_up(off + 4 * ne, 256);
+    const size_t o_sz = off; off = align_up(off + sizeof(svt::Sizes), 256);
+    svt_status st = dev_alloc(c, &p->buf, off);
+    if (st != SVT_OK) {
+        delete p;
+        return st;
+    }
+    p->buf_bytes = off;
+    char *base = static_cast<char *>(p->buf);
+    p->in = svt_event_batch{0, 0, 0, SVT_MEM_DEVICE,
+                            reinterpret_cast<const int32_t *>(base + o_ro),
+                            reinterpret_cast<const uint8_t *>(base + o_sec),
+                            reinterpret_cast<const uint8_t *>(base + o_nh),
+                            reinterpret_cast<const int32_t *>(base + o_ho),
+                            reinterpret_cast<const int16_t *>(base + o_hits),
+                            reinterpret_cast<const int16_t *>(base + o_xft)};
+    p->out = svt_results{reinterpret_cast<int32_t *>(base + o_ncomb),
+                         reinterpret_cast<int32_t *>(base + o_np),
+                         reinterpret_cast<int32_t *>(base + o_best),
+                         reinterpret_cast<uint64_t *>(base + o_chi2),
+                         reinterpret_cast<int32_t *>(base + o_par),
+                         reinterpret_cast<uint8_t *>(base + o_hi),
+                         reinterpret_cast<int32_t *>(base + o_ntr), nullptr, SVT_MEM_DEVICE, 0};
+    p->sizes_dev = reinterpret_cast<svt::Sizes *>(base + o_sz);
+    p->grid = c->cu_count * p->tuning.blocks_per_cu;
+    if (hipHostMalloc(reinterpret_cast<void **>(&p->sizes_host), sizeof(svt::Sizes),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&p->partials),
+                      sizeof(svt::BlockPartial) * p->grid,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        st = hip_fail(hipGetLastError(), "hipHostMalloc");
+        plan_free(p);
+        return st;
+    }
+    memset(p->sizes_host, 0, sizeof(svt::Sizes));
+    memset(p->partials, 0, sizeof(svt::BlockPartial) * p->grid);
+
+    svt::FitArgs a;
+    memset(&a, 0, sizeof a);
+    a.road_offsets = p->in.road_offsets;
+    a.sector = p->in.sector;
+    a.nhits4 = reinterpret_cast<const uint32_t *>(p->in.nhits);
+    a.hit_offsets = p->in.hit_offsets;
+    a.hits = p->in.hits;
+    a.xft2 = reinterpret_cast<const uint32_t *>(p->in.xft);
+    a.sizes = p->sizes_dev;
+    a.n_sectors = c->n_sectors;
+    a.coef = c->coef;
+    a.offset = c->offset;
+    a.cut_d = (double)c->cut;
+    a.ncomb = p->out.ncomb;
+    a.npass = p->out.npass;
+    a.best = p->out.best;
+    a.chi2 = p->out.chi2;
+    a.params = p->out.params;
+    a.hit_index4 = reinterpret_cast<uint32_t *>(p->out.hit_index);
+    a.ntracks = p->out.ntracks;
+    a.events_per_chunk = p->tuning.events_per_chunk;
+    a.schedule = p->tuning.schedule;
+    a.partials = static_cast<svt::BlockPartial *>(const_cast<void *>(device_view(p->partials, SVT_MEM_MAPPED)));
+
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = hipMemcpyAsync(p->sizes_dev, p->sizes_host, sizeof(svt::Sizes),
+                                       hipMemcpyHostToDevice, cs);
+        hipError_t e2 = svt::launch_fit(a, p->grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, cs);
+        e = hipStreamEndCapture(cs, &p->graph);
+        if (e == hipSuccess && e1 != hipSuccess) e = e1;
+        if (e == hipSuccess && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "plan capture");
+        plan_free(p);
+        return st;
+    }
+    *out = p;
+    return SVT_OK;
+}
+
+svt_status svt_plan_destroy(svt_plan *p)
+{
+    if (p == nullptr) return SVT_E_INVAL;
+    DeviceGuard g(p->ctx->device);
+    if (p->busy) {
+        for (int i = 0; i < kSlots; ++i) {
+            Slot &s = p->ctx->slots[i];
+            if (s.busy && s.plan == p) {
+                (void)hipEventSynchronize(s.ev_end);
+                s.plan = nullptr;
+                s.busy = false;
+            }
+        }
+    }
+    plan_free(p);
+    return SVT_OK;
+}
+
+svt_status svt_plan_buffers(svt_plan *p, svt_event_batch *in, svt_results *out)
+{
+    if (p == nullptr) return SVT_E_INVAL;
+    if (in) {
+        *in = p->in;
+        in->n_events = p->max_events;
+        in->n_roads = p->max_roads;
+        in->n_hits = p->max_hits;
+    }
+    if (out) *out = p->out;
+    return SVT_OK;
+}
+
+svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results *res,
+                        void *hip_stream, svt_ticket *ticket)
+{
+    if (p == nullptr || b == nullptr || res == nullptr || ticket == nullptr) return SVT_E_INVAL;
+    svt_ctx *c = p->ctx;
+    const svt_status vs = check_call(b, res);
+    if (vs != SVT_OK) return vs;
+    const int32_t ne = b->n_events, nr = b->n_roads, nh = b->n_hits;
+    if (ne > p->max_events || nr > p->max_roads || nh > p->max_hits) return SVT_E_INVAL;
+    if (res->comb_offsets && res->mem_kind != SVT_MEM_DEVICE) return SVT_E_INVAL;
+    if (!c->loaded || c->const_gen != p->const_gen) return SVT_E_STATE;
+    if (p->busy) return SVT_E_AGAIN;
+    const int si = (int)(c->next_ticket % kSlots);
+    Slot &s = c->slots[si];
+    if (s.busy) return SVT_E_AGAIN;
+    DeviceGuard g(c->device);
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    if (res->comb_offsets) {
+        svt_status r = ensure(c, s.scan, svt::comb_offsets_scratch_bytes(nr));
+        if (r != SVT_OK) return r;
+    }
+
+    HIP_TRY(hipEventRecord(s.ev_start, st));
+    // inputs into the plan's buffers (skipped when the caller filled them in place)
+    const void *src[6] = {b->road_offsets, b->sector, b->nhits, b->hit_offsets, b->hits, b->xft};
+    const void *dst[6] = {p->in.road_offsets, p->in.sector, p->in.nhits, p->in.hit_offsets,
+                          p->in.hits, p->in.xft};
+    const size_t bytes[6] = {4 * ((size_t)ne + 1), (size_t)nr, 4 * (size_t)nr,
+                             4 * ((size_t)nr + 1), 2 * (size_t)nh, 4 * (size_t)nr};
+    for (int i = 0; i < 6; ++i)
+        if (bytes[i] && src[i] != dst[i])
+            HIP_TRY(hipMemcpyAsync(const_cast<void *>(dst[i]), src[i], bytes[i], hipMemcpyDefault, st));
+    p->sizes_host->n_events = ne;
+    p->sizes_host->n_roads = nr;
+    p->sizes_host->n_hits = nh;
+    p->sizes_host->seq = (uint32_t)c->next_ticket;
+    HIP_TRY(hipGraphLaunch(p->exec, st));
+    if (res->comb_offsets) {
+        hipError_t e = svt::launch_comb_offsets(p->out.ncomb, res->comb_offsets, nr,
+                                                static_cast<int64_t *>(s.scan.ptr), st);
+        if (e != hipSuccess) return hip_fail(e, "comb_offsets launch");
+    }
+    // results out of the plan's buffers (skipped when the caller reads them in place)
+    const void *rs[7] = {p->out.ncomb, p->out.npass, p->out.best, p->out.chi2, p->out.params,
+                         p->out.hit_index, p->out.ntracks};
+    void *rd[7] = {res->ncomb, res->npass, res->best, res->chi2, res->params, res->hit_index,
+                   res->ntracks};
+    const size_t rb[7] = {4 * (size_t)nr, 4 * (size_t)nr, 4 * (size_t)nr, 8 * (size_t)nr,
+                          12 * (size_t)nr, 4 * (size_t)nr, 4 * (size_t)ne};
+    for (int i = 0; i < 7; ++i)
+        if (rb[i] && rd[i] != rs[i]) HIP_TRY(hipMemcpyAsync(rd[i], rs[i], rb[i], hipMemcpyDefault, st));
+    HIP_TRY(hipEventRecord(s.ev_end, st));
+    s.busy = true;
+    s.ticket = c->next_ticket++;
+    s.parts = p->partials;
+    s.grid = p->grid;
+    s.plan = p;
+    p->busy = true;
+    *ticket = s.ticket;
+    return SVT_OK;
 }
 
 }  // extern "C"

@@ -78,6 +78,14 @@ SIGNATURES = {
     "svt_set_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
     "svt_get_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
     "svt_get_device_info": (ctypes.c_int32, [P, ctypes.POINTER(svt_device_info)]),
+    "svt_plan_create": (ctypes.c_int32, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         P, ctypes.POINTER(P)]),
+    "svt_plan_destroy": (ctypes.c_int32, [P]),
+    "svt_plan_buffers": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch),
+                                          ctypes.POINTER(svt_results)]),
+    "svt_plan_fit": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch),
+                                      ctypes.POINTER(svt_results), P,
+                                      ctypes.POINTER(ctypes.c_int64)]),
     "svt_shadow_forward": (ctypes.c_int32, [P, ctypes.POINTER(svt_shadow_tracks), P, P, P, P, P]),
     "svt_shadow_backward": (ctypes.c_int32, [P, ctypes.POINTER(svt_shadow_tracks), P, P, P, P, P,
                                              P, P, P]),
@@ -250,6 +258,32 @@ class DeviceResults:
         if self.comb_offsets is not None:
             out["comb_offsets"] = self.comb_offsets.cpu().numpy()
         return out
+
+
+def svt_plan_create(ctx, max_events, max_roads, max_hits, events_per_chunk=0, blocks_per_cu=0,
+                    schedule=0):
+    h = P()
+    t = svt_tuning(int(events_per_chunk), int(blocks_per_cu), int(schedule), 0)
+    check(lib.svt_plan_create(ctx, int(max_events), int(max_roads), int(max_hits),
+                              ctypes.byref(t), ctypes.byref(h)), "svt_plan_create")
+    return h
+
+
+def svt_plan_destroy(plan):
+    return lib.svt_plan_destroy(plan)
+
+
+def svt_plan_buffers(plan):
+    b, r = svt_event_batch(), svt_results()
+    check(lib.svt_plan_buffers(plan, ctypes.byref(b), ctypes.byref(r)), "svt_plan_buffers")
+    return b, r
+
+
+def svt_plan_fit(plan, batch: svt_event_batch, res: svt_results, stream=None):
+    t = ctypes.c_int64(0)
+    st = lib.svt_plan_fit(plan, ctypes.byref(batch), ctypes.byref(res),
+                          None if stream is None else P(stream), ctypes.byref(t))
+    return st, t.value
 
 
 class Context:
