@@ -10,6 +10,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <vector>
 
 #include "svt.h"
 #include "svt_internal.h"
@@ -75,6 +76,7 @@ struct svt_ctx {
     Slot slots[kSlots];
     svt_ticket next_ticket = 1;
     DevBuf shadow_scratch;                   // float-shadow partial sums
+    std::vector<DevBuf> pool;                // idle staging buffers
     uint64_t const_gen = 0;                  // bumped by every svt_load_constants
     svt_tuning tuning{0, 3, 1, 0};  // auto chunk, 3 blocks/CU, cyclic
 };
@@ -153,6 +155,43 @@ svt_status ensure(svt_ctx *c, DevBuf &b, size_t bytes)
 }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Staging buffers of requests in flight come from a pool: best fit among the
+// idle buffers, else a new allocation, first releasing idle buffers when the
+// budget requires it.  SVT_E_NOMEM means the in-flight requests leave no
+// room for this one now.
+svt_status stage_acquire(svt_ctx *c, DevBuf &out, size_t bytes)
+{
+    int best = -1;
+    for (int i = 0; i < (int)c->pool.size(); ++i)
+        if (c->pool[i].cap >= bytes && (best < 0 || c->pool[i].cap < c->pool[best].cap)) best = i;
+    if (best >= 0) {
+        out = c->pool[best];
+        c->pool.erase(c->pool.begin() + best);
+        return SVT_OK;
+    }
+    const size_t want = align_up(bytes, (size_t)1 << 20);
+    while (c->budget && c->used + want > c->budget && !c->pool.empty()) {
+        int big = 0;
+        for (int i = 1; i < (int)c->pool.size(); ++i)
+            if (c->pool[i].cap > c->pool[big].cap) big = i;
+        dev_free(c, c->pool[big].ptr, c->pool[big].cap);
+        c->pool.erase(c->pool.begin() + big);
+    }
+    void *p = nullptr;
+    svt_status st = dev_alloc(c, &p, want);
+    if (st != SVT_OK) return st;
+    out.ptr = p;
+    out.cap = want;
+    return SVT_OK;
+}
+
+void stage_release(svt_ctx *c, DevBuf &b)
+{
+    if (b.ptr) c->pool.push_back(b);
+    b.ptr = nullptr;
+    b.cap = 0;
+}
 
 bool kind_ok(int32_t k) { return k >= SVT_MEM_PAGEABLE && k <= SVT_MEM_DEVICE; }
 
@@ -293,6 +332,7 @@ svt_status svt_destroy(svt_ctx *c)
     }
     if (c->coef) (void)hipFree(c->coef);
     if (c->shadow_scratch.ptr) (void)hipFree(c->shadow_scratch.ptr);
+    for (DevBuf &b : c->pool) (void)hipFree(b.ptr);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return SVT_OK;
@@ -408,14 +448,24 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         o_ntr = off; off = align_up(off + b_ntr, 256);
         o_co = off; off = align_up(off + b_co, 256);
     }
-    if (off) {
-        svt_status r = ensure(c, s.stage, off);
-        if (r != SVT_OK) return r;
-    }
     if (res->comb_offsets) {
         svt_status r = ensure(c, s.scan, svt::comb_offsets_scratch_bytes(nr));
         if (r != SVT_OK) return r;
     }
+    if (off) {
+        svt_status r = stage_acquire(c, s.stage, off);
+        if (r != SVT_OK) return r;
+    }
+    // the staging buffer goes back to the pool unless the request is submitted
+    struct StageGuard {
+        svt_ctx *c;
+        DevBuf *b;
+        bool keep = false;
+        ~StageGuard()
+        {
+            if (!keep) stage_release(c, *b);
+        }
+    } guard{c, &s.stage};
     char *base = static_cast<char *>(s.stage.ptr);
 
     svt::FitArgs a;
@@ -510,6 +560,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         if (co_dev) HIP_TRY(hipMemcpyAsync(res->comb_offsets, co_dev, b_co, k, st));
     }
     HIP_TRY(hipEventRecord(s.ev_end, st));
+    guard.keep = true;
     s.busy = true;
     s.ticket = c->next_ticket++;
     *ticket = s.ticket;
@@ -573,6 +624,7 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     }
     if (s.plan) s.plan->busy = false;
     s.plan = nullptr;
+    stage_release(c, s.stage);
     s.busy = false;
     s.ticket = -1;
     return status;
