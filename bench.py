@@ -1,12 +1,15 @@
 """Benchmark of the SVT linearized fit on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections fit,uneven,serve,io,shadow]
 
-One step = one svt_fit_events request over the scaled-up plain-fit workload
-(3000 events x 64 roads, 1-4 hits per layer, 72 sectors, lattice constants,
-planted tracks; 192,000 roads, ~7.5 M combinations) with inputs and results
-resident in HBM.  Inputs rotate over distinct copies so that the timed
-passes read HBM rather than the 256 MB last-level cache.  Prints one JSON line.
+Headline step = one svt_fit_events request over the scaled-up plain-fit
+workload (3000 events x 64 roads, 1-4 hits per layer, 72 sectors, lattice
+constants, half the roads with a planted track: 192,000 roads, ~7.5 M
+combinations), inputs and results resident in HBM.  Inputs rotate over
+distinct copies so timed passes read HBM rather than the 256 MB last-level
+cache.  Further sections measure the uneven-batch plan against per-event
+launches, the serving loop (p50/p99 per burst, batched against plain), the
+transfer study and the float shadow.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,25 +27,30 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(batch) -> int:
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n_events, n_roads, n_hits, n_sectors=72):
     """Bytes the method must move once: every input word read once, every
-    result word written once (constants: 12 KB, once per launch)."""
-    nr, ne, nh = batch.n_roads, batch.n_events, batch.n_hits
-    inputs = 4 * (ne + 1) + nr * (1 + 4 + 4 + 4) + 4 + 2 * nh
-    outputs = nr * (4 + 4 + 4 + 8 + 12 + 4) + 4 * ne
-    consts = 72 * 42 * 4
-    return inputs + outputs + consts
+    result word written once, the constants once."""
+    inputs = 4 * (n_events + 1) + n_roads * (1 + 4 + 4 + 4) + 4 + 2 * n_hits
+    outputs = n_roads * (4 + 4 + 4 + 8 + 12 + 4) + 4 * n_events
+    return inputs + outputs + n_sectors * 42 * 4
 
 
-def cpu_baseline(batch, consts, min_seconds=10.0, max_reps=50):
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q))
+
+
+def cpu_baseline(batch, consts, min_seconds=10.0, max_reps=200):
     import oracle
     oracle.build(force=False)
     threads = max(1, min(16, os.cpu_count() or 1))
-    total = 0
-    reps = 0
+    total = reps = 0
     t0 = time.perf_counter()
     while reps < max_reps:
-        rc, out, summ = oracle.fit_batch(batch, consts, n_threads=threads, comb_offsets=False)
+        rc, _, summ = oracle.fit_batch(batch, consts, n_threads=threads, comb_offsets=False)
         assert rc == 0
         total += summ["total_comb"]
         reps += 1
@@ -50,7 +58,210 @@ def cpu_baseline(batch, consts, min_seconds=10.0, max_reps=50):
             break
     dt = time.perf_counter() - t0
     return {"value": total / dt, "unit": "combinations/s", "cores": threads, "kind": "oracle",
-            "sample": f"full 3000-event batch x {reps} passes ({dt:.1f} s), OpenMP over events"}
+            "sample": f"the full 3000-event batch, {reps} passes in {dt:.1f} s "
+                      f"(OpenMP over events, {threads} threads)"}
+
+
+def section_fit(args, svt, synth, torch):
+    batch, consts = synth.cfg2()
+    ctx = svt.Context(0)
+    ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+    info = ctx.device_info()
+    copies = [svt.to_device(batch) for _ in range(args.copies)]
+    results = [svt.DeviceResults(batch.n_events, batch.n_roads) for _ in range(args.copies)]
+    bs = [c.struct() for c in copies]
+    rs = [r.struct() for r in results]
+    stream = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+
+    def run(n):
+        pend, dev_ns, total = [], [], 0
+        for i in range(n):
+            pend.append(ctx.submit(bs[i % args.copies], rs[i % args.copies], stream))
+            if len(pend) > 32:
+                st, s = ctx.result(pend.pop(0), -1)
+                svt.check(st, "fit")
+                total += s.total_comb
+                dev_ns.append(s.device_ns)
+        for t in pend:
+            st, s = ctx.result(t, -1)
+            svt.check(st, "fit")
+            total += s.total_comb
+            dev_ns.append(s.device_ns)
+        return total, dev_ns
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total, dev_ns = run(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # one request at a time: the request's own device time without queueing
+    iso = []
+    for i in range(20):
+        t = ctx.submit(bs[i % args.copies], rs[i % args.copies], stream)
+        st, s = ctx.result(t, -1)
+        iso.append(s.device_ns)
+    kernel_s = float(np.mean(dev_ns)) * 1e-9
+    alg = algorithmic_bytes(batch.n_events, batch.n_roads, batch.n_hits)
+    achieved = alg / kernel_s / 1e9
+    out = dict(
+        value=total / elapsed, ms_per_step=elapsed * 1e3 / args.steps,
+        combinations=int(total // args.steps),
+        config={"workload": "scaled-up plain fit: 3000 events x 64 roads, 1-4 hits per layer, "
+                            "72 sectors, lattice constants, half the roads with a planted track",
+                "n_events": batch.n_events, "n_roads": batch.n_roads, "n_hits": batch.n_hits,
+                "combinations": int(total // args.steps), "chi2_cut": consts.chi2_cut,
+                "device": info["arch"], "compute_units": info["compute_units"],
+                "tuning": ctx.tuning(), "input_copies": args.copies},
+        roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                  "kernel_us": kernel_s * 1e6, "algorithmic_bytes": alg,
+                  "isolated_request_us_p50": pct(iso, 50) / 1e3},
+        batch=batch, consts=consts)
+    ctx.close()
+    return out
+
+
+def section_uneven(args, svt, synth, torch, uneven):
+    batch, consts = synth.cfg3()
+    ctx = svt.Context(0)
+    ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+    db = svt.to_device(batch)
+    dr = svt.DeviceResults(batch.n_events, batch.n_roads)
+    best, table = uneven.autotune(ctx, db, dr, reps=5)
+    plan = uneven.Plan(ctx, batch.n_events, batch.n_roads, batch.n_hits, best)
+    b, r = db.struct(), dr.struct()
+    inb, outb = plan.inb, plan.outb
+    plan.fit(b, r)                       # inputs now in the plan's buffers
+    inb.n_events, inb.n_roads, inb.n_hits = batch.n_events, batch.n_roads, batch.n_hits
+    lat = []
+    for _ in range(args.uneven_reps):
+        t0 = time.perf_counter()
+        st, s = plan.fit(inb, outb)
+        lat.append(time.perf_counter() - t0)
+        svt.check(st)
+    dev = []
+    for _ in range(args.uneven_reps):
+        st, s = plan.fit(inb, outb)
+        dev.append(s.device_ns)
+    per = uneven.PerEventBatches(batch)
+    per.run(ctx)                         # warm
+    plain_wall, plain_dev = [], None
+    for _ in range(3):
+        w, dns, _ = per.run(ctx)
+        plain_wall.append(w)
+        plain_dev = dns
+    plan.close()
+    ctx.close()
+    total = int(np.prod(batch.nhits.astype(np.int64), axis=1).sum())
+    return {"workload": "uneven batching: 10000 events, roads/event geometric (mean 16, max 256), "
+                        "hits/layer Poisson(1.5) clipped to [1, 8]",
+            "combinations": total, "tuning": best, "tuning_candidates": len(table),
+            "batched_graph_us_p50": pct(lat, 50) * 1e6, "batched_graph_us_p99": pct(lat, 99) * 1e6,
+            "batched_graph_device_us_p50": pct(dev, 50) / 1e3,
+            "plain_per_event_batch_us_p50": pct(plain_wall, 50) * 1e6,
+            "plain_per_event_device_us_p50": pct(plain_dev, 50) / 1e3,
+            "plain_per_event_device_us_p99": pct(plain_dev, 99) / 1e3,
+            "batched_fits_per_s": total / pct(lat, 50),
+            "plain_fits_per_s": total / pct(plain_wall, 50)}
+
+
+def section_serve(args, svt, synth, torch, serve):
+    batch, consts = synth.cfg2(seed=5)
+    out = {"workload": "trigger serving: Poisson bursts of 1-3000 events (log-uniform), "
+                       "events shaped as the 3000-event plain fit, pinned host pool",
+           "loads": []}
+    pool = serve.HostPool(batch)
+    comb_road = np.prod(batch.nhits.astype(np.int64), axis=1)
+    comb_cum = np.concatenate([[0], np.cumsum(comb_road)])[batch.road_offsets.astype(np.int64)]
+    for load, nb_batched, nb_plain in ((1e4, args.serve_bursts[0], args.serve_bursts[0]),
+                                       (1e5, args.serve_bursts[1], args.serve_bursts[1]),
+                                       (1e6, args.serve_bursts[2], args.serve_bursts[2] // 2)):
+        rng = np.random.default_rng(int(load) % 1000 + 5)
+        arr = serve.make_arrivals(rng, nb_batched, load, pool.batch.n_events)
+        ctx = svt.Context(0, 4 << 30)
+        ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+        srv = serve.Server(serve.LibraryDevice(ctx, 4), pool, n_slots=4, max_events=6000)
+        srv.warm()                         # staging buffers for the largest launches
+        srv.run(arr[:8])
+        srv.launch_sizes.clear()
+        t0 = time.perf_counter()
+        recs = srv.run(arr)
+        wall = time.perf_counter() - t0
+        ev = sum(r.e1 - r.e0 for r in recs)
+        comb = sum(int(comb_cum[r.e1] - comb_cum[r.e0]) for r in recs)
+        st_b = serve.latency_stats(recs)
+        plain = serve.PlainServer(ctx, pool, window=32)
+        precs = plain.run(arr[:nb_plain], time_limit=60.0)
+        st_p = serve.latency_stats(precs)
+        ctx.close()
+        out["loads"].append({"events_per_s": load, "bursts": len(recs),
+                             "batched": dict(st_b, launches=len(srv.launch_sizes),
+                                             mean_events_per_launch=float(np.mean(srv.launch_sizes)),
+                                             events_per_s_served=ev / wall,
+                                             fits_per_s=comb / wall),
+                             "plain": dict(st_p, bursts=len(precs))})
+        log(f"serve load {load:g}: batched p50 {st_b.get('p50_us', 0):.0f} us p99 "
+            f"{st_b.get('p99_us', 0):.0f} us | plain p50 {st_p.get('p50_us', 0):.0f} us "
+            f"p99 {st_p.get('p99_us', 0):.0f} us")
+    return out
+
+
+def section_io(args, svt, synth, torch, iostudy):
+    batch, consts = synth.cfg2(seed=5)
+    ctx = svt.Context(0)
+    ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+    sweep = iostudy.transfer_sweep(ctx, reps=9)
+    rt = iostudy.round_trip(ctx, batch, reps=5)
+    ctx.close()
+    return {"transfers": sweep, "round_trip": rt}
+
+
+def section_shadow(args, svt, synth, torch, shadow):
+    h = synth.helix_tracks(args.shadow_tracks, seed=4)
+    coef, off = synth.pilot_constants(h)
+    # start away from the optimum, as before a calibration
+    rng = np.random.default_rng(5)
+    coef = (coef * (1 + rng.normal(0, 0.02, coef.shape))).astype(np.float32)
+    off = (off + rng.normal(0, 5.0, off.shape)).astype(np.float32)
+    ctx = svt.Context(0)
+    tr = shadow.ShadowTracks.from_helix(h, (1 / 400.0, 1 / 1e4, 1.0))
+    A = torch.tensor(coef, device="cuda")
+    b = torch.tensor(off, device="cuda")
+    for _ in range(3):
+        shadow.forward(ctx.handle, tr, A, b)
+        shadow.backward(ctx.handle, tr, A, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        shadow.forward(ctx.handle, tr, A, b)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_us = e0.elapsed_time(e1) * 1e3 / reps
+    e0.record()
+    for _ in range(reps):
+        shadow.backward(ctx.handle, tr, A, b)
+    e1.record()
+    torch.cuda.synchronize()
+    bwd_us = e0.elapsed_time(e1) * 1e3 / reps
+    t0 = time.perf_counter()
+    res = shadow.calibrate(ctx.handle, tr, A, b, steps=args.shadow_steps, lr=args.shadow_lr, lam=10.0,
+                           record_every=max(1, args.shadow_steps // 5))
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / args.shadow_steps
+    ci, oi, sh, status = shadow.requantize(ctx.handle, res.coef, res.offset)
+    torch.cuda.synchronize()
+    ctx.close()
+    nbytes = h.x.shape[0] * (6 + 3) * 4
+    return {"workload": f"float-shadow calibration: {h.x.shape[0]} helix tracks, 72 sectors",
+            "forward_us": fwd_us, "backward_us": bwd_us,
+            "backward_gbs": nbytes / (bwd_us * 1e-6) / 1e9,
+            "calibration_step_ms": step_ms, "loss_history": res.history,
+            "requantize_status": int(status.item()),
+            "shifts": [int(v) for v in sh.cpu().numpy()[:8]]}
 
 
 def main():
@@ -59,85 +270,56 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--copies", type=int, default=32)
+    ap.add_argument("--sections", default="fit,uneven,serve,io,shadow")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--uneven-reps", type=int, default=50)
+    ap.add_argument("--serve-bursts", type=lambda s: [int(v) for v in s.split(",")],
+                    default=[40, 150, 400])
+    ap.add_argument("--shadow-tracks", type=int, default=1000000)
+    ap.add_argument("--shadow-steps", type=int, default=50)
+    ap.add_argument("--shadow-lr", type=float, default=1e-4)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the fit path has no cross-GPU step)", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_1311_0380_amd import svt, synth
+    from paper_1311_0380_amd import iostudy, serve, shadow, svt, synth, uneven
 
-    batch, consts = synth.cfg2()
-    ctx = svt.Context(0)
-    ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
-    info = ctx.device_info()
-    copies = [svt.to_device(batch) for _ in range(args.copies)]
-    results = [svt.DeviceResults(batch.n_events, batch.n_roads) for _ in range(args.copies)]
-    bstructs = [c.struct() for c in copies]
-    rstructs = [r.struct() for r in results]
-    stream = torch.cuda.current_stream().cuda_stream
-    torch.cuda.synchronize()
-
-    def run(n, collect):
-        tickets = []
-        dev_ns = []
-        total = 0
-        for i in range(n):
-            k = i % args.copies
-            tickets.append(ctx.submit(bstructs[k], rstructs[k], stream))
-            if len(tickets) > 32:
-                st, s = ctx.result(tickets.pop(0), -1)
-                svt.check(st, "fit")
-                total += s.total_comb
-                dev_ns.append(s.device_ns)
-        for t in tickets:
-            st, s = ctx.result(t, -1)
-            svt.check(st, "fit")
-            total += s.total_comb
-            dev_ns.append(s.device_ns)
-        return total, dev_ns
-
-    run(args.warmup, False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    total, dev_ns = run(args.steps, True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    ms_per_step = elapsed * 1e3 / args.steps
-    fits_per_s = total / elapsed
-    kernel_s = float(np.mean(dev_ns)) * 1e-9
-    alg = algorithmic_bytes(batch)
-    achieved = alg / kernel_s / 1e9
+    sections = set(args.sections.split(","))
+    log("section fit")
+    fit = section_fit(args, svt, synth, torch)
     line = {
         "metric": "fitted combinations/s (+ p50/p99 per-burst latency, batched vs plain)",
-        "value": fits_per_s,
-        "unit": "combinations/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32/fp64-exact",
-        "data": "synthetic (seeded generator; paper's CDF data not available)",
-        "config": {"workload": "scaled-up plain fit: 3000 events x 64 roads, 1-4 hits/layer, "
-                               "72 sectors, lattice constants, half the roads with a planted track",
-                   "n_roads": batch.n_roads, "n_hits": batch.n_hits,
-                   "combinations": int(total // args.steps), "chi2_cut": consts.chi2_cut,
-                   "device": info["arch"], "compute_units": info["compute_units"],
-                   "tuning": ctx.tuning(), "input_copies": args.copies},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel_us": kernel_s * 1e6, "algorithmic_bytes": alg},
+        "value": fit["value"], "unit": "combinations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": fit["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32 fit rows, fp64 exact chi2",
+        "data": "synthetic (seeded generators; the paper's CDF data is not available)",
+        "config": fit["config"], "roofline": fit["roofline"],
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(batch, consts, args.cpu_seconds)
-    ctx.close()
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(fit["batch"], fit["consts"], args.cpu_seconds)
+    if "uneven" in sections:
+        log("section uneven")
+        line["uneven"] = section_uneven(args, svt, synth, torch, uneven)
+    if "serve" in sections:
+        log("section serve")
+        line["serve"] = section_serve(args, svt, synth, torch, serve)
+        p = {f"{int(l['events_per_s'])}": {"batched_p50_us": l["batched"].get("p50_us"),
+                                            "batched_p99_us": l["batched"].get("p99_us"),
+                                            "plain_p50_us": l["plain"].get("p50_us"),
+                                            "plain_p99_us": l["plain"].get("p99_us")}
+             for l in line["serve"]["loads"]}
+        line["per_burst_latency_us"] = p
+    if "io" in sections:
+        log("section io")
+        line["io"] = section_io(args, svt, synth, torch, iostudy)
+    if "shadow" in sections:
+        log("section shadow")
+        line["shadow"] = section_shadow(args, svt, synth, torch, shadow)
     print(json.dumps(line))
 
 

@@ -154,7 +154,7 @@ svt_status svt_load_constants(svt_ctx *ctx, int32_t n_sectors, const int32_t *co
  * Fit every road of a batch (asynchronous).  Copies host inputs to device
  * staging (PAGEABLE, PINNED), or reads them in place (MAPPED, DEVICE), runs
  * the fit, and copies results back when they are host memory.  hip_stream is
- * a hipStream_t (NULL = the context's stream).  The caller keeps every
+ * a hipStream_t (NULL = the null stream, as everywhere in HIP).  The caller keeps every
  * buffer alive and unmodified until svt_result() has returned something other
  * than SVT_E_AGAIN for *ticket.  Errors returned here: SVT_E_INVAL,
  * SVT_E_STATE (no constants), SVT_E_NOMEM (staging over budget), SVT_E_AGAIN
@@ -193,6 +193,17 @@ typedef struct {
 } svt_device_info;
 svt_status svt_get_device_info(svt_ctx *ctx, svt_device_info *info);
 
+/* Transfer probe for the I/O study (the one-GPU analog of the paper's
+ * comparison of copy strategies, Sec. 4.2): reps transfers of `bytes` between
+ * a fresh host buffer of the given kind and device memory, timed one by one
+ * with events on the context's stream; *median_us receives the median.
+ * kind: SVT_MEM_PAGEABLE or SVT_MEM_PINNED (DMA copies), SVT_MEM_MAPPED (a
+ * kernel reading / writing the mapped host buffer in place).  direction:
+ * 0 = host to device, 1 = device to host.  Allocates and frees its buffers
+ * (device memory counts against the context's budget). */
+svt_status svt_io_probe(svt_ctx *ctx, int32_t kind, int32_t direction, size_t bytes,
+                        int32_t reps, double *median_us);
+
 /* ------------------------------------------------------------------------
  * Plans: uneven batches fitted by one persistent, graph-captured launch.
  * A plan owns device buffers for a batch of up to max_events / max_roads /
@@ -229,7 +240,7 @@ svt_status svt_plan_fit(svt_plan *plan, const svt_event_batch *batch, const svt_
  *   L = (1/N) sum_t [ sum_{k<3} w_k (y_k - tau_k)^2 + sum_{k>=3} y_k^2 ]
  *       + lambda sum_s || C_s C_s^T - I ||_F^2       (C_s: rows 3..5 of sector s)
  * All pointers below are device memory; calls are asynchronous on hip_stream
- * (NULL = the context's stream).  Shadow calls on one context must not run
+ * (NULL = the null stream).  Shadow calls on one context must not run
  * concurrently on different streams (they share the context's scratch).
  * Errors: SVT_E_INVAL (NULL, counts out of range), SVT_E_NOMEM, SVT_E_DEVICE.
  * ------------------------------------------------------------------------ */

@@ -16,6 +16,10 @@
 #include "svt_internal.h"
 #include "svt_shadow.h"
 
+namespace svt {
+hipError_t launch_zero_copy(const void *src, void *dst, size_t bytes, int cus, hipStream_t st);
+}
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -416,7 +420,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     if (s.busy) return SVT_E_AGAIN;
 
     DeviceGuard g(c->device);
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
 
     // byte layout of inputs and results
     const size_t b_ro = sizeof(int32_t) * ((size_t)ne + 1), b_sec = (size_t)nr,
@@ -650,7 +654,7 @@ svt_status svt_shadow_forward(svt_ctx *c, const svt_shadow_tracks *t, const floa
     svt::ShadowCall sc{t->x, t->tau, t->sector_offsets, t->n_tracks, t->n_sectors,
                        {t->w[0], t->w[1], t->w[2]}, coef, offset, y, loss,
                        nullptr, nullptr, nullptr, nullptr};
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
     hipError_t e = svt::launch_shadow_forward(sc, static_cast<double *>(c->shadow_scratch.ptr), st);
     return e == hipSuccess ? SVT_OK : hip_fail(e, "shadow forward launch");
 }
@@ -669,7 +673,7 @@ svt_status svt_shadow_backward(svt_ctx *c, const svt_shadow_tracks *t, const flo
     svt::ShadowCall sc{t->x, t->tau, t->sector_offsets, t->n_tracks, t->n_sectors,
                        {t->w[0], t->w[1], t->w[2]}, coef, offset, nullptr, nullptr,
                        grad_coef, grad_offset, grad_coef_f32, grad_offset_f32};
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
     hipError_t e = svt::launch_shadow_backward(sc, scale, static_cast<double *>(c->shadow_scratch.ptr), st);
     return e == hipSuccess ? SVT_OK : hip_fail(e, "shadow backward launch");
 }
@@ -682,7 +686,7 @@ svt_status svt_shadow_penalty(svt_ctx *c, int32_t n_sectors, const float *coef, 
         grad_coef == nullptr)
         return SVT_E_INVAL;
     DeviceGuard g(c->device);
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
     hipError_t e = svt::launch_shadow_penalty(coef, n_sectors, lambda, value, grad_coef, grad_coef_f32, st);
     return e == hipSuccess ? SVT_OK : hip_fail(e, "shadow penalty launch");
 }
@@ -695,7 +699,7 @@ svt_status svt_shadow_adam(svt_ctx *c, int32_t n, float *param, const double *gr
         return SVT_E_INVAL;
     if (n == 0) return SVT_OK;
     DeviceGuard g(c->device);
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
     hipError_t e = svt::launch_adam(n, param, grad, m, v, lr, beta1, beta2, eps, step, st);
     return e == hipSuccess ? SVT_OK : hip_fail(e, "adam launch");
 }
@@ -708,7 +712,7 @@ svt_status svt_requantize(svt_ctx *c, int32_t n_sectors, const float *coef, cons
         !offset_int || !shift || !status || max_abs < 1)
         return SVT_E_INVAL;
     DeviceGuard g(c->device);
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
     hipError_t e = svt::launch_requantize(coef, offset, n_sectors, max_abs, coef_int, offset_int,
                                           shift, status, st);
     return e == hipSuccess ? SVT_OK : hip_fail(e, "requantize launch");
@@ -904,7 +908,7 @@ svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results
     Slot &s = c->slots[si];
     if (s.busy) return SVT_E_AGAIN;
     DeviceGuard g(c->device);
-    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
     if (res->comb_offsets) {
         svt_status r = ensure(c, s.scan, svt::comb_offsets_scratch_bytes(nr));
         if (r != SVT_OK) return r;
@@ -947,6 +951,70 @@ svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results
     s.plan = p;
     p->busy = true;
     *ticket = s.ticket;
+    return SVT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// I/O probe
+// ---------------------------------------------------------------------------
+svt_status svt_io_probe(svt_ctx *c, int32_t kind, int32_t direction, size_t bytes, int32_t reps,
+                        double *median_us)
+{
+    if (c == nullptr || median_us == nullptr || reps < 1 || bytes == 0 ||
+        (direction != 0 && direction != 1) ||
+        (kind != SVT_MEM_PAGEABLE && kind != SVT_MEM_PINNED && kind != SVT_MEM_MAPPED))
+        return SVT_E_INVAL;
+    DeviceGuard g(c->device);
+    void *dev = nullptr;
+    svt_status st = dev_alloc(c, &dev, bytes);
+    if (st != SVT_OK) return st;
+    void *host = nullptr;
+    hipError_t e = hipSuccess;
+    if (kind == SVT_MEM_PAGEABLE) {
+        host = malloc(bytes);
+        if (host == nullptr) {
+            dev_free(c, dev, bytes);
+            return SVT_E_NOMEM;
+        }
+    } else {
+        e = hipHostMalloc(&host, bytes,
+                          kind == SVT_MEM_MAPPED ? (hipHostMallocMapped | hipHostMallocCoherent)
+                                                 : hipHostMallocDefault);
+        if (e != hipSuccess) {
+            dev_free(c, dev, bytes);
+            return hip_fail(e, "hipHostMalloc");
+        }
+    }
+    memset(host, 1, bytes);
+    std::vector<double> t;
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    const void *hview = kind == SVT_MEM_MAPPED ? device_view(host, SVT_MEM_MAPPED) : host;
+    for (int r = 0; r < reps + 1 && e == hipSuccess; ++r) {
+        e = hipEventRecord(a, c->stream);
+        if (e != hipSuccess) break;
+        if (kind == SVT_MEM_MAPPED)
+            e = direction == 0 ? svt::launch_zero_copy(hview, dev, bytes, c->cu_count, c->stream)
+                               : svt::launch_zero_copy(dev, const_cast<void *>(hview), bytes,
+                                                       c->cu_count, c->stream);
+        else
+            e = direction == 0 ? hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream)
+                               : hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) break;
+        e = hipEventRecord(b, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && r > 0) t.push_back((double)ms * 1e3);   // first one warms up
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (kind == SVT_MEM_PAGEABLE) free(host); else (void)hipHostFree(host);
+    dev_free(c, dev, bytes);
+    if (e != hipSuccess) return hip_fail(e, "io probe");
+    std::sort(t.begin(), t.end());
+    *median_us = t[t.size() / 2];
     return SVT_OK;
 }
 

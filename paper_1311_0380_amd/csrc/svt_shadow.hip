@@ -180,13 +180,22 @@ __global__ void shadow_bwd_reduce(const double *part, int32_t n_sectors, int32_t
     }
 }
 
-// Pass 2 of the forward: all slices in order, one thread.
-__global__ void shadow_fwd_reduce(const double *part, int32_t n_blocks, double inv_n, double *loss)
+// Pass 2 of the forward: one block; thread i sums blocks i, i + 256, ... in
+// order, then a fixed shuffle tree and the waves in order.
+__global__ void __launch_bounds__(kSBlock) shadow_fwd_reduce(const double *part, int32_t n_blocks,
+                                                             double inv_n, double *loss)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double s_w[kSWaves];
     double t = 0.0;
-    for (int k = 0; k < n_blocks; ++k) t += part[(size_t)k * kNG + 42];
-    loss[0] = t * inv_n;
+    for (int k = threadIdx.x; k < n_blocks; k += kSBlock) t += part[(size_t)k * kNG + 42];
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double u = 0.0;
+        for (int w = 0; w < kSWaves; ++w) u += s_w[w];
+        loss[0] = u * inv_n;
+    }
 }
 
 // Orthonormality penalty of the constraint rows, one thread per sector, then
@@ -293,7 +302,7 @@ hipError_t launch_shadow_forward(const ShadowCall &c, double *scratch, hipStream
             c.w[0], c.w[1], c.w[2], c.coef, c.offset, c.y, scratch};
     const int nb = c.n_sectors * a.slices;
     hipLaunchKernelGGL(shadow_fwd, dim3(nb), dim3(kSBlock), 0, st, a);
-    hipLaunchKernelGGL(shadow_fwd_reduce, dim3(1), dim3(64), 0, st, scratch, nb,
+    hipLaunchKernelGGL(shadow_fwd_reduce, dim3(1), dim3(kSBlock), 0, st, scratch, nb,
                        c.n_tracks > 0 ? 1.0 / c.n_tracks : 0.0, c.loss);
     return hipGetLastError();
 }

@@ -188,6 +188,46 @@ class Server:
         self.results = {}
         self.launch_sizes = []
 
+    def warm(self):
+        """One full-size launch per slot, all in flight together, so that the
+        device's staging pool holds buffers for the largest launches before
+        the first burst arrives."""
+        ranges, ne, nr, nh = [], 0, 0, 0
+        while True:
+            ce, cr, ch = self.pool.counts(0, self.pool.batch.n_events)
+            room = (self.max_events - ne, self.max_roads - nr, self.max_hits - nh)
+            if ce <= room[0] and cr <= room[1] and ch <= room[2]:
+                ranges.append((0, self.pool.batch.n_events))
+                ne, nr, nh = ne + ce, nr + cr, nh + ch
+                continue
+            # the largest prefix of the pool that still fits
+            lo, hi = 0, self.pool.batch.n_events
+            while lo < hi:
+                mid = (lo + hi + 1) // 2
+                ce, cr, ch = self.pool.counts(0, mid)
+                if ce <= room[0] and cr <= room[1] and ch <= room[2]:
+                    lo = mid
+                else:
+                    hi = mid - 1
+            if lo:
+                ranges.append((0, lo))
+            break
+        tickets = []
+        for slot in range(len(self.bufs)):
+            self.bufs[slot].fill(self.pool, ranges)
+            st, t = self.device.submit(slot, self.bufs[slot])
+            if st != 0:
+                raise RuntimeError(f"warm-up submit failed with status {st}")
+            tickets.append(t)
+        for t in tickets:
+            while True:
+                self.clock()
+                fin, st = self.device.poll(t)
+                if fin:
+                    if st != 0:
+                        raise RuntimeError(f"warm-up launch failed with status {st}")
+                    break
+
     def run(self, arrivals):
         """Serve the bursts; returns their records (latencies in seconds)."""
         recs = [BurstRecord(i, a, e0, e1) for i, (a, e0, e1) in enumerate(arrivals)]

@@ -78,6 +78,8 @@ SIGNATURES = {
     "svt_set_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
     "svt_get_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
     "svt_get_device_info": (ctypes.c_int32, [P, ctypes.POINTER(svt_device_info)]),
+    "svt_io_probe": (ctypes.c_int32, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t,
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "svt_plan_create": (ctypes.c_int32, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          P, ctypes.POINTER(P)]),
     "svt_plan_destroy": (ctypes.c_int32, [P]),
@@ -258,6 +260,13 @@ class DeviceResults:
         if self.comb_offsets is not None:
             out["comb_offsets"] = self.comb_offsets.cpu().numpy()
         return out
+
+
+def svt_io_probe(ctx, kind, direction, nbytes, reps=20):
+    us = ctypes.c_double(0.0)
+    check(lib.svt_io_probe(ctx, int(kind), int(direction), int(nbytes), int(reps),
+                           ctypes.byref(us)), "svt_io_probe")
+    return us.value
 
 
 def svt_plan_create(ctx, max_events, max_roads, max_hits, events_per_chunk=0, blocks_per_cu=0,

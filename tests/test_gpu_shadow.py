@@ -112,6 +112,7 @@ def test_calibration_reduces_loss_and_rescore(env, oracle_lib):
     res = env["shadow"].calibrate(env["handle"], env["tracks"], dev(env, coef), dev(env, off),
                                   steps=60, lr=2e-3, lam=10.0, record_every=20)
     losses = [l for _, l, _ in res.history]
+    assert all(np.isfinite(l) and l >= 0 for l in losses)
     start, _ = osh.data_loss(coef, off, h.x.astype(np.float32), h.truth.astype(np.float32),
                              h.sector_offsets, W)
     assert losses[-1] < start
@@ -135,3 +136,24 @@ def test_calibration_reduces_loss_and_rescore(env, oracle_lib):
     rc, want, _ = oracle_lib.fit_batch(b, synth.Constants(ci, oi, cut))
     assert rc == 0
     assert_equal_results(got, want)
+
+
+def test_default_stream_ordering(env):
+    """Library calls on torch's default stream (handle 0) are ordered with
+    torch's own work on it: a copy issued right after the backward sees the
+    finished gradient, at a size where the backward takes tens of µs."""
+    torch = env["torch"]
+    h = synth.helix_tracks(1000000, seed=45)
+    coef, off = synth.pilot_constants(h)
+    tr = env["shadow"].ShadowTracks.from_helix(h, W)
+    A, b = dev(env, coef), dev(env, off)
+    assert torch.cuda.current_stream().cuda_stream == 0
+    for _ in range(3):
+        g64, o64, _, _ = env["shadow"].backward(env["handle"], tr, A, b)
+        early = torch.cat([g64.reshape(-1), o64.reshape(-1)]).clone()
+        loss, _ = env["shadow"].forward(env["handle"], tr, A, b)
+        early_loss = loss.item()
+        torch.cuda.synchronize()
+        late = torch.cat([g64.reshape(-1), o64.reshape(-1)])
+        assert torch.equal(early, late)
+        assert np.isfinite(early_loss) and early_loss == loss.item() and early_loss >= 0

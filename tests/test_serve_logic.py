@@ -124,3 +124,17 @@ def test_arrivals_shape():
     assert np.all(np.diff(t) > 0) and sizes.min() >= 1 and sizes.max() <= 3000
     rate = sizes.sum() / t[-1]
     assert 0.8e5 < rate < 1.25e5
+
+
+def test_warm_fills_every_slot_to_the_launch_limits():
+    clock = FakeClock()
+    pool = serve.HostPool(pool_batch(), pin=False)
+    dev = SimDevice(clock, budget_bytes=1 << 30)
+    srv = serve.Server(dev, pool, n_slots=3, max_events=900, clock=clock, pin_memory=False)
+    srv.warm()
+    assert sorted(s for s, _ in dev.submitted) == [0, 1, 2]
+    for _, (ne, nr, nh) in dev.submitted:
+        assert ne <= srv.max_events and nr <= srv.max_roads and nh <= srv.max_hits
+        # two whole pools (800 events) plus the largest prefix that still fits
+        assert ne == 900 or nr > srv.max_roads - 70 or nh > srv.max_hits - 70 * 16
+    assert not dev.inflight
