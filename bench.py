@@ -39,6 +39,32 @@ def algorithmic_bytes(n_events, n_roads, n_hits, n_sectors=72):
     return inputs + outputs + n_sectors * 42 * 4
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("svt_fit.hip", "svt_internal.h"):
+        with open(os.path.join(ROOT, "paper_1311_0380_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the kernel source that is built now; else None."""
+    path = os.path.join(ROOT, "profiles", "fit_kernel_3000ev_hbm_counters.md")
+    try:
+        kv = {}
+        for line in open(path):
+            if "=" in line and not line.startswith(("|", "`", "cd ")):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("kernel_sha256_prefix") != kernel_source_hash():
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
@@ -115,7 +141,7 @@ def section_fit(args, svt, synth, torch):
                 "device": info["arch"], "compute_units": info["compute_units"],
                 "tuning": ctx.tuning(), "input_copies": args.copies},
         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                  "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                   "kernel_us": kernel_s * 1e6, "algorithmic_bytes": alg,
                   "isolated_request_us_p50": pct(iso, 50) / 1e3},
         batch=batch, consts=consts)
@@ -264,6 +290,26 @@ def section_shadow(args, svt, synth, torch, shadow):
             "shifts": [int(v) for v in sh.cpu().numpy()[:8]]}
 
 
+def section_copy(args, torch):
+    """A plain device-to-device copy of known size: the yardstick that turns
+    the HBM counters of a profile into bytes."""
+    n = 512 << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return {"bytes_read": n, "bytes_written": n, "us": us, "gbs": 2 * n / us / 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +366,9 @@ def main():
     if "shadow" in sections:
         log("section shadow")
         line["shadow"] = section_shadow(args, svt, synth, torch, shadow)
+    if "copy" in sections:
+        log("section copy")
+        line["copy"] = section_copy(args, torch)
     print(json.dumps(line))
 
 
