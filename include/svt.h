@@ -118,12 +118,17 @@ typedef struct {
                                command (copies included)                          */
 } svt_summary;
 
-/* Launch shape of the fit kernel; 0 in any field keeps the current value. */
+/* Launch shape of the fit.  Kernel 0 (default) gives each wavefront its own
+ * chunk of events (at most 63 events per chunk; it aims for 64 roads);
+ * kernel 1 gives each block a chunk (it aims for 256 roads).  Results are the
+ * same bit for bit either way. */
 typedef struct {
     int32_t events_per_chunk;  /* events per work item (1..256); 0 = automatic    */
-    int32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu (1..16)   */
-    int32_t schedule;          /* 1 = cyclic (item w -> block w mod grid), 2 = blocked */
-    int32_t reserved;
+    int32_t blocks_per_cu;     /* grid = CUs * blocks_per_cu (1..16), fewer when
+                                  there are fewer chunks; 0 = automatic           */
+    int32_t schedule;          /* 1 = cyclic (item w -> worker w mod workers),
+                                  2 = blocked; 0 keeps the current value          */
+    int32_t kernel;            /* 0 = wavefront per chunk, 1 = block per chunk    */
 } svt_tuning;
 
 /*

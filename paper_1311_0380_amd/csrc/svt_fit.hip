@@ -10,20 +10,18 @@
 //      binned by (n2, n3) so that a wavefront's rows share their inner trip
 //      counts; the hits are staged in LDS as fp64 (coalesced, flattened);
 //      the constraint rows' constant part b + A[:,4] x4 + A[:,5] x5 is formed.
-//   B  one thread per row (i0, i1): z = base + A[:,0] h0 + A[:,1] h1, then for
-//      every (i2, i3) the three constraint rows y3..y5 and chi2 in fp64.  Every
-//      value is an integer below 2^53 whenever chi2 <= cut < 2^48, so the pass
-//      test, the pass count and the minimum are exact; larger chi2 round to
-//      values that still exceed the cut.  The row's best (chi2, i2, i3) is
-//      merged into the road with one LDS atomicMin on the key
+//   B  one thread per row (i0, i1): z = base + A[:,0] h0 + A[:,1] h1, then
+//      every (i2, i3) combination in the row loops of svt_rows.h.  The row's
+//      best is merged into the road with one LDS atomicMin on the key
 //      chi2 << 16 | i0 << 12 | i1 << 8 | i2 << 4 | i3, whose order is the
 //      order of (chi2, combination index k) because each i_l < n_l <= 16.
 //   C  one thread per road: decode the winner, recompute its parameter rows
 //      0..2 exactly in int32, write the road's results, count tracks per event.
 //
-// The last block to finish reduces the per-block partial sums into the request
-// summary and resets the request's counters.
+// Each block writes its partial sums to host-mapped memory; the host reduces
+// them when the request completes.
 #include "svt_internal.h"
+#include "svt_rows.h"
 
 namespace svt {
 namespace {
@@ -70,105 +68,6 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
-struct RowState {
-    double z3, z4, z5;   // constraint rows with layers 0, 1 and the XFT words
-    double a3, a4, a5;   // column of layer 2
-    double c3, c4, c5;   // column of layer 3
-    double bc;           // best chi2 of the row so far (starts at cut + 1)
-    uint32_t bidx;       // (i2 << 4) | i3 of the best, ~0 if none
-    uint32_t np;         // passing combinations
-};
-
-// One combination: the three constraint rows from q (rows with layers 0..2)
-// plus column 3 times h3, chi2, pass count, running minimum (first index wins).
-__device__ __forceinline__ void combo(RowState &st, double q3, double q4, double q5, double h3,
-                                      double cut, uint32_t idx)
-{
-    const double y3 = fma(st.c3, h3, q3);
-    const double y4 = fma(st.c4, h3, q4);
-    const double y5 = fma(st.c5, h3, q5);
-    const double c = fma(y5, y5, fma(y4, y4, y3 * y3));
-    st.np += (c <= cut) ? 1u : 0u;
-    const bool better = c < st.bc;
-    st.bc = better ? c : st.bc;
-    st.bidx = better ? idx : st.bidx;
-}
-
-// Inner loops for a wavefront whose rows share n3 (= N3).  Rows are binned
-// with n3 as the major key, so n2 may still differ: every lane runs its own
-// n2 under the wavefront's largest n2 (n2w).
-template <int N3>
-__device__ __forceinline__ void row_loop_uniform(RowState &st, const int16_t *s_hit, uint32_t p2,
-                                                 uint32_t n2, uint32_t n2w, double cut)
-{
-    const uint32_t p3 = p2 + n2;
-    if constexpr (N3 <= 8) {
-        // the layer-3 hits stay in registers across the i2 loop
-        double h3[N3];
-#pragma unroll
-        for (int i3 = 0; i3 < N3; ++i3) h3[i3] = (double)s_hit[p3 + i3];
-        for (uint32_t i2 = 0; i2 < n2w; ++i2) {
-            if (i2 < n2) {
-                const double h2 = (double)s_hit[p2 + i2];
-                const double q3 = fma(st.a3, h2, st.z3);
-                const double q4 = fma(st.a4, h2, st.z4);
-                const double q5 = fma(st.a5, h2, st.z5);
-#pragma unroll
-                for (int i3 = 0; i3 < N3; ++i3)
-                    combo(st, q3, q4, q5, h3[i3], cut, (i2 << 4) | (uint32_t)i3);
-            }
-        }
-    } else {
-        for (uint32_t i2 = 0; i2 < n2w; ++i2) {
-            if (i2 < n2) {
-                const double h2 = (double)s_hit[p2 + i2];
-                const double q3 = fma(st.a3, h2, st.z3);
-                const double q4 = fma(st.a4, h2, st.z4);
-                const double q5 = fma(st.a5, h2, st.z5);
-#pragma unroll 4
-                for (int i3 = 0; i3 < N3; ++i3)
-                    combo(st, q3, q4, q5, (double)s_hit[p3 + i3], cut, (i2 << 4) | (uint32_t)i3);
-            }
-        }
-    }
-}
-
-// Inner loops for a wavefront whose rows have different (n2, n3): indices are
-// clamped into the row's lists and combinations past the row's end get a
-// chi2 that neither passes nor wins.
-__device__ __forceinline__ void row_loop_mixed(RowState &st, const int16_t *s_hit, uint32_t p2,
-                                               uint32_t n2, uint32_t n3, uint32_t n2w,
-                                               uint32_t n3w, double cut)
-{
-    const uint32_t p3 = p2 + n2;
-    const double never = cut + 2.0;
-    for (uint32_t i2 = 0; i2 < n2w; ++i2) {
-        const uint32_t i2c = i2 < n2 ? i2 : n2 - 1;
-        const double h2 = (double)s_hit[p2 + i2c];
-        const double q3 = fma(st.a3, h2, st.z3);
-        const double q4 = fma(st.a4, h2, st.z4);
-        const double q5 = fma(st.a5, h2, st.z5);
-        for (uint32_t i3 = 0; i3 < n3w; ++i3) {
-            const uint32_t i3c = i3 < n3 ? i3 : n3 - 1;
-            const double h3 = (double)s_hit[p3 + i3c];
-            const double y3 = fma(st.c3, h3, q3);
-            const double y4 = fma(st.c4, h3, q4);
-            const double y5 = fma(st.c5, h3, q5);
-            double c = fma(y5, y5, fma(y4, y4, y3 * y3));
-            c = (i2 < n2 && i3 < n3) ? c : never;
-            st.np += (c <= cut) ? 1u : 0u;
-            const bool better = c < st.bc;
-            st.bc = better ? c : st.bc;
-            st.bidx = better ? ((i2 << 4) | i3) : st.bidx;
-        }
-    }
-}
-
-__device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
-{
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-
 struct Acc {
     uint64_t comb = 0, pass = 0;
     uint32_t tracks = 0;
@@ -195,6 +94,7 @@ constexpr int kStage = kHitCap / kBlock;    // staged hits per thread
 
 // Process the roads [s, rb) of the current chunk starting at road s; returns
 // how many roads were fitted (at least one when s < rb).
+template <bool F>
 __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int32_t s, int32_t rb,
                            int32_t n_roads, int32_t n_hits, int32_t n_sectors, int32_t ne,
                            double cut, Acc &acc)
@@ -339,7 +239,7 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         const uint32_t p2 = hbj + rn0 + rn1;
         const double *cs = s_cd + (uint32_t)S.sec[j] * kCstStride;
         const double h0v = (double)S.hit[hbj + i0], h1v = (double)S.hit[hbj + rn0 + i1];
-        RowState st;
+        Row st;
         st.z3 = fma(cs[3], h1v, fma(cs[0], h0v, S.base[0][j]));
         st.z4 = fma(cs[4], h1v, fma(cs[1], h0v, S.base[1][j]));
         st.z5 = fma(cs[5], h1v, fma(cs[2], h0v, S.base[2][j]));
@@ -349,43 +249,24 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         st.c3 = cs[9];
         st.c4 = cs[10];
         st.c5 = cs[11];
-        st.bc = cut + 1.0;
+        st.best = F ? __builtin_inf() : cut + 1.0;
         st.bidx = 0xFFFFFFFFu;
         st.np = 0;
-        // binned order: the last lane holds the largest (n3, n2) of the wavefront
-        const uint32_t n3f = __builtin_amdgcn_readfirstlane(rn3);
-        const uint32_t n3l = __builtin_amdgcn_readlane(rn3, 63);
-        if (n3f == n3l) {
-            const uint32_t n2w = __builtin_amdgcn_readlane(rn2, 63);
-            switch (n3f) {
-            case 1: row_loop_uniform<1>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 2: row_loop_uniform<2>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 3: row_loop_uniform<3>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 4: row_loop_uniform<4>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 5: row_loop_uniform<5>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 6: row_loop_uniform<6>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 7: row_loop_uniform<7>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 8: row_loop_uniform<8>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 9: row_loop_uniform<9>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 10: row_loop_uniform<10>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 11: row_loop_uniform<11>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 12: row_loop_uniform<12>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 13: row_loop_uniform<13>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 14: row_loop_uniform<14>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 15: row_loop_uniform<15>(st, S.hit, p2, rn2, n2w, cut); break;
-            case 16: row_loop_uniform<16>(st, S.hit, p2, rn2, n2w, cut); break;
-            default: break;
-            }
-        } else {
-            const uint32_t n2w = wave_max_u32(rn2);
-            row_loop_mixed(st, S.hit, p2, rn2, rn3, __builtin_amdgcn_readfirstlane(n2w), n3l, cut);
-        }
+        run_row<F>(st, S.hit, p2, rn2, rn3, F ? cut + 0.5 : cut);
         if (act) {
-            if (st.bidx != 0xFFFFFFFFu) {
-                const unsigned long long key = ((unsigned long long)st.bc << 16) |
-                                               (i0 << 12) | (i1 << 8) | st.bidx;
-                atomicMin(&S.key[j], key);
+            bool found;
+            unsigned long long c2;
+            uint32_t bidx;
+            if constexpr (F) {
+                found = st.best < cut + 1.0;
+                c2 = (unsigned long long)st.best;                       // floor: best >= 0
+                bidx = (uint32_t)((st.best - (double)c2) * 256.0);      // exact: a multiple of 2^-8
+            } else {
+                found = st.bidx != 0xFFFFFFFFu;
+                c2 = (unsigned long long)st.best;
+                bidx = st.bidx;
             }
+            if (found) atomicMin(&S.key[j], (c2 << 16) | (i0 << 12) | (i1 << 8) | bidx);
             if (st.np) atomicAdd(&S.np[j], st.np);
         }
     }
@@ -521,7 +402,8 @@ fit_kernel(FitArgs a)
         for (int i = tid; i < ne; i += kBlock) S.evcnt[i] = 0;
         __syncthreads();
         for (int32_t s = ra; s < rb;)
-            s += process_sub(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc);
+            s += a.frac_key ? process_sub<true>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc)
+                            : process_sub<false>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc);
         for (int i = tid; i < ne; i += kBlock) {
             const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
             const bool bad = lo < 0 || hi < lo || hi > n_roads || (e == 0 && lo != 0) ||

@@ -25,6 +25,18 @@ constexpr int kCstIntB = 36;      // int32 index of the constraint offsets
 constexpr int kCstIntP = 40;      // int32 index of the parameter columns
 constexpr int kCstIntPB = 58;     // int32 index of the parameter offsets
 
+// Sector tables of the wave kernel, built by svt_load_constants:
+//   pb   [n_sectors][12] fp64  columns 0..3 of constraint rows 3..5, [col * 3 + row]
+//   base [n_sectors][12] fp64  A[3..5][4], A[3..5][5], b[3..5], 3 zeros
+//   par  [n_sectors][24] int32 row k of 0..2 at [k * 8]: A[k][0..5], b[k], 0
+constexpr int kCstPbStride = 12;
+constexpr int kCstBaseStride = 12;
+constexpr int kCstParStride = 24;
+constexpr int kCstWaveBytes = (kCstPbStride + kCstBaseStride) * 8 + kCstParStride * 4;
+constexpr int kWaveMaxEvents = 63;        // events per chunk of the wave kernel
+constexpr int kWaveTargetRoads = 64;      // roads per chunk it aims for
+constexpr int kWaveBlocksPerCu = 3;       // default: 3 waves per SIMD (VGPR-limited)
+
 // Sizes of a batch when they are read from device memory (graph replay).
 struct Sizes {
     int32_t n_events, n_roads, n_hits;
@@ -67,6 +79,10 @@ struct FitArgs {
     int32_t *params;
     uint32_t *hit_index4;       // 4 x uint8 per road
     int32_t *ntracks;
+    const double *cst_pb;       // wave-kernel sector tables (device)
+    const double *cst_base;
+    const int32_t *cst_par;
+    int32_t frac_key;           // 1: cut < 2^44, minimise chi2 + index / 256
     // launch shape
     int32_t events_per_chunk;
     int32_t schedule;           // 1 cyclic, 2 blocked
@@ -77,6 +93,8 @@ struct FitArgs {
 
 hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
 hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream);
+hipError_t prepare_fit_wave();
+hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream);
 hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
                                int64_t *scratch, hipStream_t stream);
 size_t comb_offsets_scratch_bytes(int32_t n_roads);

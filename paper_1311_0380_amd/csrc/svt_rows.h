@@ -1,0 +1,316 @@
+// Row loops of the SVT fit shared by the fit kernels (arXiv:1311.0380,
+// Sec. 2): for one (i0, i1) row of a road, every (i2, i3) combination's
+// constraint rows y3..y5 and chi2 in fp64, the pass count and the best.
+//
+// Every quantity is an integer below 2^53 whenever chi2 <= cut < 2^48, so
+// the cut, the count and the minimum are exact.  When cut < 2^44 the
+// combination index rides in the fraction bits of the value being minimised,
+// chi2 + (i2 * 16 + i3) / 256, which is then exact too (the "fraction form"):
+// one v_min_f64 keeps both the smallest chi2 and, among equal ones, the
+// lowest index.  Otherwise a compare-and-select keeps them (general form).
+//
+// Rows are expected sorted by (n3, n2) within a wavefront, so that the last
+// lane holds the wavefront's largest (n3, n2); every lane is active.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace svt {
+namespace {
+
+// Orders the wave's earlier LDS writes before its later LDS reads.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// DPP controls: row_shr:n shifts within a row of 16 lanes; row_bcast:15 and
+// row_bcast:31 carry lane 15 / lane 31 into the following rows.
+constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int Ctrl, int RowMask, bool Bound>
+__device__ __forceinline__ uint32_t dpp(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, Ctrl, RowMask, 0xF, Bound);
+}
+
+// Inclusive prefix sum across the wavefront (all lanes active).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    x += dpp<kRowShr + 1, 0xF, true>(x);
+    x += dpp<kRowShr + 2, 0xF, true>(x);
+    x += dpp<kRowShr + 4, 0xF, true>(x);
+    x += dpp<kRowShr + 8, 0xF, true>(x);
+    x += dpp<kRowBcast15, 0xA, false>(x);
+    x += dpp<kRowBcast31, 0xC, false>(x);
+    return x;
+}
+
+// Maximum across the wavefront (all lanes active), as a uniform value.
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)
+{
+    x = max(x, dpp<kRowShr + 1, 0xF, true>(x));
+    x = max(x, dpp<kRowShr + 2, 0xF, true>(x));
+    x = max(x, dpp<kRowShr + 4, 0xF, true>(x));
+    x = max(x, dpp<kRowShr + 8, 0xF, true>(x));
+    x = max(x, dpp<kRowBcast15, 0xA, false>(x));
+    x = max(x, dpp<kRowBcast31, 0xC, false>(x));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+struct Row {
+    double z3, z4, z5;   // constraint rows with layers 0, 1 and the XFT words
+    double a3, a4, a5;   // column of layer 2
+    double c3, c4, c5;   // column of layer 3
+    double best;         // fraction form: chi2 + idx / 256; else chi2 of the best
+    uint32_t bidx;       // (i2 << 4) | i3 of the best (general form), ~0 if none
+    uint32_t np;         // passing combinations
+};
+
+// ---- fraction form (cut < 2^44) ------------------------------------------
+// v = chi2 + i3 / 256 is exact below 2^45; a chi2 at or above 2^45 rounds to
+// a value still above cut + 1, so v <= cut + 1/2 is exactly chi2 <= cut.
+
+// v_min_f64 without the NaN-quieting max that a library fmin puts in front
+// of it (no value here is a NaN).
+__device__ __forceinline__ double dmin(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Small rows, fully unrolled: N2 = the wavefront's largest n2, N3 = its n3
+// (uniform) or largest n3 (UNI false).  All hits are loaded up front (clamped
+// into the row's lists); i2 past the lane's n2 is masked off, i3 past its n3
+// (mixed wavefronts only) computes a duplicate with a larger fraction that
+// never wins and is kept out of the pass count.
+template <int N2, int N3, bool UNI>
+__device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
+                                           uint32_t n3, double lim)
+{
+    const uint32_t p3 = p2 + n2;
+    double h2[N2], h3[N3];
+#pragma unroll
+    for (int i = 0; i < N2; ++i) h2[i] = (double)hit[p2 + (i < (int)n2 ? (uint32_t)i : n2 - 1)];
+#pragma unroll
+    for (int i = 0; i < N3; ++i)
+        h3[i] = (double)hit[p3 + (UNI || i < (int)n3 ? (uint32_t)i : n3 - 1)];
+#pragma unroll
+    for (int i2 = 0; i2 < N2; ++i2) {
+        if (i2 == 0 || (uint32_t)i2 < n2) {
+            const double q3 = fma(st.a3, h2[i2], st.z3);
+            const double q4 = fma(st.a4, h2[i2], st.z4);
+            const double q5 = fma(st.a5, h2[i2], st.z5);
+#pragma unroll
+            for (int i3 = 0; i3 < N3; ++i3) {
+                const double y3 = fma(st.c3, h3[i3], q3);
+                const double y4 = fma(st.c4, h3[i3], q4);
+                const double y5 = fma(st.c5, h3[i3], q5);
+                const double v =
+                    fma(y5, y5, fma(y4, y4, fma(y3, y3, (i2 * 16 + i3) * (1.0 / 256))));
+                const bool pass = v <= lim && (UNI || (uint32_t)i3 < n3);
+                st.np += pass ? 1u : 0u;
+                st.best = dmin(st.best, v);
+            }
+        }
+    }
+}
+
+template <int N3>
+__device__ __forceinline__ void frac_uniform(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
+                                             uint32_t n2w, double lim)
+{
+    constexpr int H = N3 <= 8 ? N3 : 1;
+    const uint32_t p3 = p2 + n2;
+    double h3[H];
+    if constexpr (N3 <= 8) {
+#pragma unroll
+        for (int i3 = 0; i3 < N3; ++i3) h3[i3] = (double)hit[p3 + i3];
+    }
+    double h2n = (double)hit[p2];
+    double f2 = 0.0;
+    for (uint32_t i2 = 0; i2 < n2w; ++i2, f2 += 1.0 / 16) {
+        const double h2 = h2n;
+        h2n = (double)hit[p2 + (i2 + 1 < n2 ? i2 + 1 : n2 - 1)];   // next, in flight
+        if (i2 < n2) {
+            const double q3 = fma(st.a3, h2, st.z3);
+            const double q4 = fma(st.a4, h2, st.z4);
+            const double q5 = fma(st.a5, h2, st.z5);
+            double bi = __builtin_inf();
+            if constexpr (N3 <= 8) {
+#pragma unroll
+                for (int i3 = 0; i3 < N3; ++i3) {
+                    const double y3 = fma(st.c3, h3[i3], q3);
+                    const double y4 = fma(st.c4, h3[i3], q4);
+                    const double y5 = fma(st.c5, h3[i3], q5);
+                    const double v = fma(y5, y5, fma(y4, y4, fma(y3, y3, i3 * (1.0 / 256))));
+                    st.np += v <= lim ? 1u : 0u;
+                    bi = dmin(bi, v);
+                }
+            } else {
+                double f3 = 0.0;
+#pragma unroll 4
+                for (int i3 = 0; i3 < N3; ++i3, f3 += 1.0 / 256) {
+                    const double h = (double)hit[p3 + i3];
+                    const double y3 = fma(st.c3, h, q3);
+                    const double y4 = fma(st.c4, h, q4);
+                    const double y5 = fma(st.c5, h, q5);
+                    const double v = fma(y5, y5, fma(y4, y4, fma(y3, y3, f3)));
+                    st.np += v <= lim ? 1u : 0u;
+                    bi = dmin(bi, v);
+                }
+            }
+            st.best = dmin(st.best, bi + f2);
+        }
+    }
+}
+
+// Rows of different (n2, n3) in one wavefront: indices are clamped into the
+// row's lists.  A clamped duplicate has the chi2 of a real combination and a
+// larger fraction, so it never wins; it is kept out of the pass count.
+__device__ __forceinline__ void frac_mixed(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
+                                           uint32_t n3, uint32_t n2w, uint32_t n3w, double lim)
+{
+    const uint32_t p3 = p2 + n2;
+    double f2 = 0.0;
+    for (uint32_t i2 = 0; i2 < n2w; ++i2, f2 += 1.0 / 16) {
+        const double h2 = (double)hit[p2 + (i2 < n2 ? i2 : n2 - 1)];
+        const double q3 = fma(st.a3, h2, st.z3);
+        const double q4 = fma(st.a4, h2, st.z4);
+        const double q5 = fma(st.a5, h2, st.z5);
+        double bi = __builtin_inf(), f3 = 0.0;
+        for (uint32_t i3 = 0; i3 < n3w; ++i3, f3 += 1.0 / 256) {
+            const double h = (double)hit[p3 + (i3 < n3 ? i3 : n3 - 1)];
+            const double y3 = fma(st.c3, h, q3);
+            const double y4 = fma(st.c4, h, q4);
+            const double y5 = fma(st.c5, h, q5);
+            const double v = fma(y5, y5, fma(y4, y4, fma(y3, y3, f3)));
+            st.np += (v <= lim && i2 < n2 && i3 < n3) ? 1u : 0u;
+            bi = dmin(bi, v);
+        }
+        st.best = dmin(st.best, bi + f2);
+    }
+}
+
+// ---- general form (any cut < 2^48) ----------------------------------------
+
+__device__ __forceinline__ void gen_combo(Row &st, double q3, double q4, double q5, double h3,
+                                          double cut, uint32_t idx)
+{
+    const double y3 = fma(st.c3, h3, q3);
+    const double y4 = fma(st.c4, h3, q4);
+    const double y5 = fma(st.c5, h3, q5);
+    const double c = fma(y5, y5, fma(y4, y4, y3 * y3));
+    st.np += (c <= cut) ? 1u : 0u;
+    const bool better = c < st.best;
+    st.best = better ? c : st.best;
+    st.bidx = better ? idx : st.bidx;
+}
+
+template <int N3>
+__device__ __forceinline__ void gen_uniform(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
+                                            uint32_t n2w, double cut)
+{
+    const uint32_t p3 = p2 + n2;
+    for (uint32_t i2 = 0; i2 < n2w; ++i2) {
+        if (i2 < n2) {
+            const double h2 = (double)hit[p2 + i2];
+            const double q3 = fma(st.a3, h2, st.z3);
+            const double q4 = fma(st.a4, h2, st.z4);
+            const double q5 = fma(st.a5, h2, st.z5);
+#pragma unroll 4
+            for (int i3 = 0; i3 < N3; ++i3)
+                gen_combo(st, q3, q4, q5, (double)hit[p3 + i3], cut, (i2 << 4) | (uint32_t)i3);
+        }
+    }
+}
+
+__device__ __forceinline__ void gen_mixed(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
+                                          uint32_t n3, uint32_t n2w, uint32_t n3w, double cut)
+{
+    const uint32_t p3 = p2 + n2;
+    const double never = cut + 2.0;
+    for (uint32_t i2 = 0; i2 < n2w; ++i2) {
+        const double h2 = (double)hit[p2 + (i2 < n2 ? i2 : n2 - 1)];
+        const double q3 = fma(st.a3, h2, st.z3);
+        const double q4 = fma(st.a4, h2, st.z4);
+        const double q5 = fma(st.a5, h2, st.z5);
+        for (uint32_t i3 = 0; i3 < n3w; ++i3) {
+            const double h = (double)hit[p3 + (i3 < n3 ? i3 : n3 - 1)];
+            const double y3 = fma(st.c3, h, q3);
+            const double y4 = fma(st.c4, h, q4);
+            const double y5 = fma(st.c5, h, q5);
+            double c = fma(y5, y5, fma(y4, y4, y3 * y3));
+            c = (i2 < n2 && i3 < n3) ? c : never;
+            st.np += (c <= cut) ? 1u : 0u;
+            const bool better = c < st.best;
+            st.best = better ? c : st.best;
+            st.bidx = better ? ((i2 << 4) | i3) : st.bidx;
+        }
+    }
+}
+
+template <bool F>
+__device__ __forceinline__ void run_row(Row &st, const int16_t *hit, uint32_t p2, uint32_t rn2,
+                                        uint32_t rn3, double lim)
+{
+    // rows are sorted by (n3, n2): the last lane holds the wavefront's largest
+    const uint32_t n3f = __builtin_amdgcn_readfirstlane(rn3);
+    const uint32_t n3l = __builtin_amdgcn_readlane(rn3, 63);
+    const uint32_t n2w = __builtin_amdgcn_readlane(rn2, 63);
+    if constexpr (F) {
+        // both inner trip counts at most 4: the unrolled forms
+        const uint32_t n3w = n3f == n3l ? n3l : wave_max(rn3);
+        const uint32_t n2m = n3f == n3l ? n2w : wave_max(rn2);
+        if (n2m <= 4 && n3w <= 4) {
+            const uint32_t sel = ((n2m - 1) << 2) | (n3w - 1);
+#define SVT_SMALL(N2, N3)                                                             \
+    case ((N2 - 1) << 2) | (N3 - 1):                                                  \
+        if (n3f == n3l) frac_small<N2, N3, true>(st, hit, p2, rn2, rn3, lim);         \
+        else frac_small<N2, N3, false>(st, hit, p2, rn2, rn3, lim);                   \
+        return;
+            switch (sel) {
+                SVT_SMALL(1, 1) SVT_SMALL(1, 2) SVT_SMALL(1, 3) SVT_SMALL(1, 4)
+                SVT_SMALL(2, 1) SVT_SMALL(2, 2) SVT_SMALL(2, 3) SVT_SMALL(2, 4)
+                SVT_SMALL(3, 1) SVT_SMALL(3, 2) SVT_SMALL(3, 3) SVT_SMALL(3, 4)
+                SVT_SMALL(4, 1) SVT_SMALL(4, 2) SVT_SMALL(4, 3) SVT_SMALL(4, 4)
+            default: break;
+            }
+#undef SVT_SMALL
+        }
+    }
+    if (n3f == n3l) {
+#define SVT_CASE(N)                                                          \
+    case N:                                                                  \
+        if constexpr (F) frac_uniform<N>(st, hit, p2, rn2, n2w, lim);        \
+        else gen_uniform<N>(st, hit, p2, rn2, n2w, lim);                     \
+        break;
+        switch (n3f) {
+            SVT_CASE(1) SVT_CASE(2) SVT_CASE(3) SVT_CASE(4) SVT_CASE(5) SVT_CASE(6)
+            SVT_CASE(7) SVT_CASE(8) SVT_CASE(9) SVT_CASE(10) SVT_CASE(11) SVT_CASE(12)
+            SVT_CASE(13) SVT_CASE(14) SVT_CASE(15) SVT_CASE(16)
+        default: break;
+        }
+#undef SVT_CASE
+    } else {
+        const uint32_t n2m = wave_max(rn2);
+        if constexpr (F) frac_mixed(st, hit, p2, rn2, rn3, n2m, n3l, lim);
+        else gen_mixed(st, hit, p2, rn2, rn3, n2m, n3l, lim);
+    }
+}
+
+}  // namespace
+}  // namespace svt

@@ -73,6 +73,7 @@ struct svt_ctx {
     // constants
     int32_t *coef = nullptr;
     int32_t *offset = nullptr;
+    void *cst_wave = nullptr;                // sector tables of the wave kernel
     int32_t n_sectors = 0;
     uint64_t cut = 0;
     bool loaded = false;
@@ -82,7 +83,7 @@ struct svt_ctx {
     DevBuf shadow_scratch;                   // float-shadow partial sums
     std::vector<DevBuf> pool;                // idle staging buffers
     uint64_t const_gen = 0;                  // bumped by every svt_load_constants
-    svt_tuning tuning{0, 3, 1, 0};  // auto chunk, 3 blocks/CU, cyclic
+    svt_tuning tuning{0, 0, 1, 0};  // automatic chunk and occupancy, cyclic, wave kernel
 };
 
 // A captured fit of any batch up to a fixed capacity (see svt_plan_create).
@@ -211,14 +212,71 @@ const void *device_view(const void *p, int32_t kind)
     return d;
 }
 
-int auto_events_per_chunk(int32_t n_events, int32_t n_roads)
+int auto_events_per_chunk(int32_t n_events, int32_t n_roads, int target, int max_events)
 {
     if (n_events <= 0) return 1;
     const double rpe = (double)n_roads / (double)n_events;
-    int e = rpe > 0 ? (int)((double)svt::kTargetRoadsPerChunk / rpe + 0.5) : 256;
+    int e = rpe > 0 ? (int)((double)target / rpe + 0.5) : max_events;
     if (e < 1) e = 1;
-    if (e > svt::kMaxEventsPerChunk) e = svt::kMaxEventsPerChunk;
+    if (e > max_events) e = max_events;
     return e;
+}
+
+// Kernel, chunking and grid of a launch.  The wave kernel takes a chunk per
+// wavefront (4 per block), the block kernel a chunk per block.  A persistent
+// grid (graph plans) keeps the full size; otherwise the grid shrinks to the
+// number of chunks.
+struct LaunchShape {
+    int kernel;   // 0 wave, 1 block
+    int epc;      // events per chunk
+    int grid;
+};
+
+LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int32_t nr,
+                         bool persistent)
+{
+    LaunchShape ls;
+    ls.kernel = t.kernel == 1 ? 1 : 0;
+    int bpc;
+    int64_t per_block;
+    if (ls.kernel == 0) {
+        ls.epc = t.events_per_chunk > 0
+                     ? (t.events_per_chunk < svt::kWaveMaxEvents ? t.events_per_chunk
+                                                                 : svt::kWaveMaxEvents)
+                     : auto_events_per_chunk(ne, nr, svt::kWaveTargetRoads, svt::kWaveMaxEvents);
+        bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : svt::kWaveBlocksPerCu;
+        per_block = svt::kBlock / 64;
+    } else {
+        ls.epc = t.events_per_chunk > 0
+                     ? t.events_per_chunk
+                     : auto_events_per_chunk(ne, nr, svt::kTargetRoadsPerChunk,
+                                             svt::kMaxEventsPerChunk);
+        bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 3;
+        per_block = 1;
+    }
+    int64_t grid = (int64_t)c->cu_count * bpc;
+    if (!persistent) {
+        const int64_t n_chunks = ne > 0 ? ((int64_t)ne + ls.epc - 1) / ls.epc : 0;
+        const int64_t need = (n_chunks + per_block - 1) / per_block;
+        if (grid > need) grid = need;
+    }
+    if (grid < 1) grid = 1;
+    ls.grid = (int)grid;
+    return ls;
+}
+
+hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &ls,
+                         hipStream_t st)
+{
+    const char *w = static_cast<const char *>(c->cst_wave);
+    a.cst_pb = reinterpret_cast<const double *>(w);
+    a.cst_base = reinterpret_cast<const double *>(w + (size_t)256 * svt::kCstPbStride * 8);
+    a.cst_par = reinterpret_cast<const int32_t *>(
+        w + (size_t)256 * (svt::kCstPbStride + svt::kCstBaseStride) * 8);
+    a.frac_key = c->cut < (1ull << 44) ? 1 : 0;
+    a.events_per_chunk = ls.epc;
+    if (ls.kernel == 0) return svt::launch_fit_wave(a, ls.grid, st);
+    return svt::launch_fit(a, ls.grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
 }
 
 // Call-level validation shared by the fit entry points.
@@ -289,6 +347,7 @@ svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes)
     snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
     c->max_grid = c->cu_count * svt::kMaxBlocksPerCu;
     e = svt::prepare_fit();
+    if (e == hipSuccess) e = svt::prepare_fit_wave();
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "fit kernel attributes");
@@ -335,6 +394,7 @@ svt_status svt_destroy(svt_ctx *c)
         if (s.scan.ptr) (void)hipFree(s.scan.ptr);
     }
     if (c->coef) (void)hipFree(c->coef);
+    if (c->cst_wave) (void)hipFree(c->cst_wave);
     if (c->shadow_scratch.ptr) (void)hipFree(c->shadow_scratch.ptr);
     for (DevBuf &b : c->pool) (void)hipFree(b.ptr);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -364,8 +424,37 @@ svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef
         c->coef = static_cast<int32_t *>(p);
         c->offset = c->coef + 256 * 36;
     }
+    if (c->cst_wave == nullptr) {
+        svt_status st = dev_alloc(c, &c->cst_wave, (size_t)256 * svt::kCstWaveBytes);
+        if (st != SVT_OK) return st;
+    }
     HIP_TRY(hipMemcpy(c->coef, coef, sizeof(int32_t) * 36 * n_sectors, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->offset, offset, sizeof(int32_t) * 6 * n_sectors, hipMemcpyHostToDevice));
+    {
+        // wave-kernel tables (see svt_internal.h for the layout)
+        std::vector<double> pb((size_t)256 * svt::kCstPbStride, 0.0);
+        std::vector<double> bs((size_t)256 * svt::kCstBaseStride, 0.0);
+        std::vector<int32_t> par((size_t)256 * svt::kCstParStride, 0);
+        for (int s = 0; s < n_sectors; ++s) {
+            const int32_t *A = coef + s * 36, *b = offset + s * 6;
+            for (int col = 0; col < 4; ++col)
+                for (int k = 0; k < 3; ++k)
+                    pb[(size_t)s * svt::kCstPbStride + col * 3 + k] = (double)A[(3 + k) * 6 + col];
+            for (int k = 0; k < 3; ++k) {
+                bs[(size_t)s * svt::kCstBaseStride + k] = (double)A[(3 + k) * 6 + 4];
+                bs[(size_t)s * svt::kCstBaseStride + 3 + k] = (double)A[(3 + k) * 6 + 5];
+                bs[(size_t)s * svt::kCstBaseStride + 6 + k] = (double)b[3 + k];
+                for (int col = 0; col < 6; ++col)
+                    par[(size_t)s * svt::kCstParStride + k * 8 + col] = A[k * 6 + col];
+                par[(size_t)s * svt::kCstParStride + k * 8 + 6] = b[k];
+            }
+        }
+        char *w = static_cast<char *>(c->cst_wave);
+        HIP_TRY(hipMemcpy(w, pb.data(), pb.size() * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(w + pb.size() * 8, bs.data(), bs.size() * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(w + (pb.size() + bs.size()) * 8, par.data(), par.size() * 4,
+                          hipMemcpyHostToDevice));
+    }
     c->n_sectors = n_sectors;
     c->cut = chi2_cut;
     c->loaded = true;
@@ -379,9 +468,11 @@ svt_status svt_set_tuning(svt_ctx *c, const svt_tuning *t)
     if (t->events_per_chunk < 0 || t->events_per_chunk > svt::kMaxEventsPerChunk) return SVT_E_INVAL;
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > svt::kMaxBlocksPerCu) return SVT_E_INVAL;
     if (t->schedule < 0 || t->schedule > 2) return SVT_E_INVAL;
+    if (t->kernel < 0 || t->kernel > 1) return SVT_E_INVAL;
     c->tuning.events_per_chunk = t->events_per_chunk;   // 0 = automatic
-    if (t->blocks_per_cu) c->tuning.blocks_per_cu = t->blocks_per_cu;
+    c->tuning.blocks_per_cu = t->blocks_per_cu;         // 0 = automatic
     if (t->schedule) c->tuning.schedule = t->schedule;
+    c->tuning.kernel = t->kernel;
     return SVT_OK;
 }
 
@@ -529,13 +620,8 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         co_dev = static_cast<int64_t *>(const_cast<void *>(device_view(res->comb_offsets, k)));
     }
 
-    const int epc = c->tuning.events_per_chunk > 0 ? c->tuning.events_per_chunk
-                                                   : auto_events_per_chunk(ne, nr);
-    const int64_t n_chunks = ne > 0 ? ((int64_t)ne + epc - 1) / epc : 0;
-    int64_t grid = (int64_t)c->cu_count * c->tuning.blocks_per_cu;
-    if (grid > n_chunks) grid = n_chunks;
-    if (grid < 1) grid = 1;
-    a.events_per_chunk = epc;
+    const LaunchShape ls = launch_shape(c, c->tuning, ne, nr, false);
+    const int64_t grid = ls.grid;
     a.schedule = c->tuning.schedule;
     a.partials = static_cast<svt::BlockPartial *>(
         const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
@@ -544,7 +630,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     s.parts = s.partials;
     s.plan = nullptr;
 
-    hipError_t e = svt::launch_fit(a, (int)grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
+    hipError_t e = launch_shaped(c, a, ls, st);
     if (e != hipSuccess) return hip_fail(e, "fit kernel launch");
     if (co_dev) {
         e = svt::launch_comb_offsets(a.ncomb, co_dev, nr, static_cast<int64_t *>(s.scan.ptr), st);
@@ -751,16 +837,17 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
     if (tuning) {
         if (tuning->events_per_chunk < 0 || tuning->events_per_chunk > svt::kMaxEventsPerChunk ||
             tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > svt::kMaxBlocksPerCu ||
-            tuning->schedule < 0 || tuning->schedule > 2) {
+            tuning->schedule < 0 || tuning->schedule > 2 || tuning->kernel < 0 ||
+            tuning->kernel > 1) {
             delete p;
             return SVT_E_INVAL;
         }
         if (tuning->events_per_chunk) p->tuning.events_per_chunk = tuning->events_per_chunk;
         if (tuning->blocks_per_cu) p->tuning.blocks_per_cu = tuning->blocks_per_cu;
         if (tuning->schedule) p->tuning.schedule = tuning->schedule;
+        p->tuning.kernel = tuning->kernel;
     }
-    if (p->tuning.events_per_chunk == 0)
-        p->tuning.events_per_chunk = auto_events_per_chunk(max_events, max_roads);
+    const LaunchShape ls = launch_shape(c, p->tuning, max_events, max_roads, true);
     p->const_gen = c->const_gen;
 
     // buffer layout: inputs, then results, then the size descriptor
@@ -802,7 +889,7 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
                          reinterpret_cast<uint8_t *>(base + o_hi),
                          reinterpret_cast<int32_t *>(base + o_ntr), nullptr, SVT_MEM_DEVICE, 0};
     p->sizes_dev = reinterpret_cast<svt::Sizes *>(base + o_sz);
-    p->grid = c->cu_count * p->tuning.blocks_per_cu;
+    p->grid = ls.grid;
     if (hipHostMalloc(reinterpret_cast<void **>(&p->sizes_host), sizeof(svt::Sizes),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&p->partials),
@@ -835,7 +922,6 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
     a.params = p->out.params;
     a.hit_index4 = reinterpret_cast<uint32_t *>(p->out.hit_index);
     a.ntracks = p->out.ntracks;
-    a.events_per_chunk = p->tuning.events_per_chunk;
     a.schedule = p->tuning.schedule;
     a.partials = static_cast<svt::BlockPartial *>(const_cast<void *>(device_view(p->partials, SVT_MEM_MAPPED)));
 
@@ -845,7 +931,7 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
     if (e == hipSuccess) {
         hipError_t e1 = hipMemcpyAsync(p->sizes_dev, p->sizes_host, sizeof(svt::Sizes),
                                        hipMemcpyHostToDevice, cs);
-        hipError_t e2 = svt::launch_fit(a, p->grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, cs);
+        hipError_t e2 = launch_shaped(c, a, ls, cs);
         e = hipStreamEndCapture(cs, &p->graph);
         if (e == hipSuccess && e1 != hipSuccess) e = e1;
         if (e == hipSuccess && e2 != hipSuccess) e = e2;

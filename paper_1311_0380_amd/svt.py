@@ -48,7 +48,7 @@ class svt_summary(ctypes.Structure):
 
 class svt_tuning(ctypes.Structure):
     _fields_ = [("events_per_chunk", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("kernel", ctypes.c_int32)]
 
 
 class svt_device_info(ctypes.Structure):
@@ -171,15 +171,15 @@ def svt_status_string(status: int) -> str:
     return lib.svt_status_string(int(status)).decode()
 
 
-def svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=0, schedule=0):
-    t = svt_tuning(int(events_per_chunk), int(blocks_per_cu), int(schedule), 0)
+def svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=0, schedule=0, kernel=0):
+    t = svt_tuning(int(events_per_chunk), int(blocks_per_cu), int(schedule), int(kernel))
     return lib.svt_set_tuning(ctx, ctypes.byref(t))
 
 
 def svt_get_tuning(ctx) -> dict:
     t = svt_tuning()
     check(lib.svt_get_tuning(ctx, ctypes.byref(t)))
-    return {f: getattr(t, f) for f, _ in t._fields_ if f != "reserved"}
+    return {f: getattr(t, f) for f, _ in t._fields_}
 
 
 def svt_get_device_info(ctx) -> dict:
@@ -270,9 +270,9 @@ def svt_io_probe(ctx, kind, direction, nbytes, reps=20):
 
 
 def svt_plan_create(ctx, max_events, max_roads, max_hits, events_per_chunk=0, blocks_per_cu=0,
-                    schedule=0):
+                    schedule=0, kernel=0):
     h = P()
-    t = svt_tuning(int(events_per_chunk), int(blocks_per_cu), int(schedule), 0)
+    t = svt_tuning(int(events_per_chunk), int(blocks_per_cu), int(schedule), int(kernel))
     check(lib.svt_plan_create(ctx, int(max_events), int(max_roads), int(max_hits),
                               ctypes.byref(t), ctypes.byref(h)), "svt_plan_create")
     return h

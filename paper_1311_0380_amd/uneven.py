@@ -20,6 +20,9 @@ CACHE_PATH = os.environ.get(
                  "svt_tune.json"))
 
 
+CACHE_VERSION = "shapes2"     # bump when the candidate set or the kernels change
+
+
 def workload_signature(n_events, n_roads, n_hits, ncomb_total=None):
     rpe = n_roads / max(1, n_events)
     hpr = n_hits / max(1, n_roads)
@@ -30,17 +33,22 @@ def workload_signature(n_events, n_roads, n_hits, ncomb_total=None):
 
 
 def candidates(n_events, n_roads):
+    """Launch shapes to try: the wavefront-per-chunk kernel around 16..128
+    roads per chunk and the block-per-chunk kernel around 128..512, each with
+    a few occupancies and both schedules."""
     rpe = max(1.0, n_roads / max(1, n_events))
     out = []
-    for e in (1, 2, 4, 8, 16, 32, 64, 128):
-        roads = e * rpe
-        if roads < 32 or roads > 1024:
-            continue
-        for bpc in (2, 3, 4):
-            for sch in (1, 2):
-                out.append(dict(events_per_chunk=e, blocks_per_cu=bpc, schedule=sch))
+    for e in (1, 2, 4, 8, 16, 32, 63):
+        if 16 <= e * rpe <= 128 or (e == 1 and rpe > 128):
+            for bpc in (3, 4):
+                for sch in (1, 2):
+                    out.append(dict(events_per_chunk=e, blocks_per_cu=bpc, schedule=sch, kernel=0))
+    for e in (1, 2, 4, 8, 16, 32, 64, 128, 256):
+        if 128 <= e * rpe <= 512 or (e == 1 and rpe > 512):
+            for bpc in (2, 3):
+                out.append(dict(events_per_chunk=e, blocks_per_cu=bpc, schedule=1, kernel=1))
     if not out:
-        out = [dict(events_per_chunk=0, blocks_per_cu=b, schedule=1) for b in (2, 3, 4)]
+        out = [dict(events_per_chunk=0, blocks_per_cu=0, schedule=1, kernel=k) for k in (0, 1)]
     return out
 
 
@@ -62,7 +70,7 @@ def autotune(ctx: svt.Context, dbatch: svt.DeviceBatch, dres: svt.DeviceResults,
     info = ctx.device_info()
     arch_key = arch_key or f"{info['arch']}_{info['compute_units']}cu"
     signature = signature or workload_signature(dbatch.n_events, dbatch.n_roads, dbatch.n_hits)
-    key = f"{arch_key}/{signature}"
+    key = f"{arch_key}/{signature}/{CACHE_VERSION}"
     cache = {}
     if use_cache and os.path.exists(CACHE_PATH):
         try:
@@ -102,7 +110,7 @@ class Plan:
         self.ctx = ctx
         self.handle = svt.svt_plan_create(ctx.handle, max_events, max_roads, max_hits,
                                           t.get("events_per_chunk", 0), t.get("blocks_per_cu", 0),
-                                          t.get("schedule", 0))
+                                          t.get("schedule", 0), t.get("kernel", 0))
         self.inb, self.outb = svt.svt_plan_buffers(self.handle)
 
     def close(self):
