@@ -31,7 +31,8 @@ constexpr int kWStage = kWHitCap / 64;
 constexpr int kWaves = kBlock / 64;
 
 struct WaveLds {
-    double road[kWRoads][4];            // base of rows 3..5, packed road info
+    double road[kWRoads][6];            // base of rows 3..5, packed road info, 2 pad
+                                        // (48-byte stride: no LDS bank-group clash)
     unsigned long long key[kWRoads];    // best key of each road
     uint32_t np[kWRoads];               // passing combinations of each road
     uint32_t evcnt[kWRoads];            // tracks of each event of the chunk
@@ -75,6 +76,14 @@ __device__ int wave_sub(const FitArgs &a, WaveLds &W, const double *s_pb, int32_
     ok = ok && (r != 0 || h0 == 0) && (r != n_roads - 1 || h1 == n_hits);
     ok = ok && xa >= 0 && xa < 4096 && xb >= 0 && xb < 4096;
     if (inr && !ok) acc.err_road = min(acc.err_road, (uint32_t)r);
+    // the sector's constants for the base of rows 3..5, in flight with the
+    // hit words below
+    double cb[9];
+    {
+        const double *src = a.cst_base + (size_t)(ok ? sec : 0u) * kCstBaseStride;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) cb[q] = src[q];
+    }
 
     // hits (<= 64 per road) and rows (<= 256 per road) of the roads before
     // this one, packed in one 32-bit scan (totals stay below 2^16)
@@ -110,13 +119,9 @@ __device__ int wave_sub(const FitArgs &a, WaveLds &W, const double *s_pb, int32_
     // the road's record: base of rows 3..5 (exact in int32, held as fp64)
     // and its packed counts, hit base and sector
     if (active) {
-        double b3 = 0.0, b4 = 0.0, b5 = 0.0;
-        if (ok) {
-            const double *cb = a.cst_base + (size_t)sec * kCstBaseStride;
-            b3 = fma(cb[3], (double)xb, fma(cb[0], (double)xa, cb[6]));
-            b4 = fma(cb[4], (double)xb, fma(cb[1], (double)xa, cb[7]));
-            b5 = fma(cb[5], (double)xb, fma(cb[2], (double)xa, cb[8]));
-        }
+        const double b3 = fma(cb[3], (double)xb, fma(cb[0], (double)xa, cb[6]));
+        const double b4 = fma(cb[4], (double)xb, fma(cb[1], (double)xa, cb[7]));
+        const double b5 = fma(cb[5], (double)xb, fma(cb[2], (double)xa, cb[8]));
         const unsigned long long info = (unsigned long long)(ok ? nh4 : 0u) |
                                         ((unsigned long long)hb << 32) |
                                         ((unsigned long long)(ok ? sec : 0u) << 48);
@@ -128,13 +133,18 @@ __device__ int wave_sub(const FitArgs &a, WaveLds &W, const double *s_pb, int32_
         W.np[lane] = 0u;
     }
 
-    // order the roads by (n3, n2) with a stable 8-bit radix sort across the
-    // lanes; roads without rows sort last
+    // order the roads by (n3, n2) with a stable radix sort across the lanes,
+    // over the key bits that occur (roads without rows hold no rows, so
+    // where they land does not matter)
     const uint32_t rows_a = active ? rows : 0u;
-    uint32_t pv = ((rows_a ? (((n3 - 1u) << 4) | (n2 - 1u)) : 255u) << 8) | (uint32_t)lane;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const bool one = (pv >> (8 + b)) & 1u;
+    const uint32_t k2 = rows_a ? n2 - 1u : 0u, k3 = rows_a ? n3 - 1u : 0u;
+    const uint32_t m2 = wave_max(k2), m3 = wave_max(k3);
+    const uint32_t b2 = m2 ? 32u - (uint32_t)__builtin_clz(m2) : 0u;
+    const uint32_t b3 = m3 ? 32u - (uint32_t)__builtin_clz(m3) : 0u;
+    uint32_t pv = (((k3 << 4) | k2) << 8) | (uint32_t)lane;
+    for (uint32_t t = 0; t < b2 + b3; ++t) {
+        const uint32_t bit = t < b2 ? t : 4u + (t - b2);
+        const bool one = (pv >> (8 + bit)) & 1u;
         const uint64_t m1 = __ballot(one);
         const uint32_t n_zero = 64u - (uint32_t)__popcll(m1);
         const uint32_t dst = one ? n_zero + lanes_below(m1) : lanes_below(~m1);
@@ -279,31 +289,45 @@ __device__ int wave_sub(const FitArgs &a, WaveLds &W, const double *s_pb, int32_
     return L;
 }
 
+// The chunks of this wavefront: 1 = cyclic (chunk c -> wave c mod waves),
+// 2 = blocked (each wave a contiguous range).
+struct ChunkRange {
+    int32_t c0, step, c1;
+};
+
+__device__ __forceinline__ ChunkRange chunk_range(const FitArgs &a, int32_t n_chunks)
+{
+    const int32_t gw = (int32_t)blockIdx.x * kWaves + (int32_t)(threadIdx.x >> 6);
+    const int32_t nw = (int32_t)gridDim.x * kWaves;
+    if (a.schedule == 2)
+        return ChunkRange{(int32_t)((int64_t)n_chunks * gw / nw), 1,
+                          (int32_t)((int64_t)n_chunks * (gw + 1) / nw)};
+    return ChunkRange{gw, nw, n_chunks};
+}
+
+// Event boundaries of chunk c: lane e holds road_offsets[c * E + e] for
+// e <= ne, a large value above.
+__device__ __forceinline__ int32_t chunk_bounds(const FitArgs &a, int32_t c, int32_t n_events)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t eb = c * a.events_per_chunk;
+    const int32_t ne = min(a.events_per_chunk, n_events - eb);
+    return lane <= ne ? a.road_offsets[eb + lane] : 0x7FFFFFFF;
+}
+
 template <bool F>
 __device__ __forceinline__ void run_chunks(const FitArgs &a, WaveLds &W, const double *s_pb,
                                            int32_t n_events, int32_t n_roads, int32_t n_hits,
-                                           Acc &acc)
+                                           const ChunkRange cr, int32_t ro_first, Acc &acc)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t gw = (int32_t)blockIdx.x * kWaves + (int32_t)(threadIdx.x >> 6);
-    const int32_t nw = (int32_t)gridDim.x * kWaves;
     const int32_t E = a.events_per_chunk;
-    const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
-    int32_t c0, step, c1;
-    if (a.schedule == 2) {
-        c0 = (int32_t)((int64_t)n_chunks * gw / nw);
-        c1 = (int32_t)((int64_t)n_chunks * (gw + 1) / nw);
-        step = 1;
-    } else {
-        c0 = gw;
-        c1 = n_chunks;
-        step = nw;
-    }
+    const int32_t c0 = cr.c0, step = cr.step, c1 = cr.c1;
     for (int32_t c = c0; c < c1; c += step) {
         const int32_t eb = c * E;
         const int32_t ne = min(E, n_events - eb);
         // event boundaries: lane e holds road_offsets[eb + e] for e <= ne
-        const int32_t ro_e = lane <= ne ? a.road_offsets[eb + lane] : 0x7FFFFFFF;
+        const int32_t ro_e = c == c0 ? ro_first : chunk_bounds(a, c, n_events);
         const int32_t ro_n = __shfl_down(ro_e, 1, 64);
         if (lane < ne) {
             const int32_t e = eb + lane;
@@ -338,7 +362,12 @@ fit_wave_kernel(FitArgs a)
         n_hits = a.sizes->n_hits;
         seq = a.sizes->seq;
     }
-    // columns 0..3 of the constraint rows of every sector -> LDS
+    // the first chunk's event boundaries are in flight while the columns 0..3
+    // of every sector's constraint rows are staged in LDS
+    const int32_t n_chunks =
+        n_events > 0 ? (n_events + a.events_per_chunk - 1) / a.events_per_chunk : 0;
+    const ChunkRange cr = chunk_range(a, n_chunks);
+    const int32_t ro_first = cr.c0 < cr.c1 ? chunk_bounds(a, cr.c0, n_events) : 0;
     double *s_pb = reinterpret_cast<double *>(s_dyn);
     for (int i = tid; i < a.n_sectors * kCstPbStride; i += kBlock) s_pb[i] = a.cst_pb[i];
     __syncthreads();
@@ -346,9 +375,9 @@ fit_wave_kernel(FitArgs a)
     Acc acc;
     WaveLds &W = s_w[tid >> 6];
     if (a.frac_key)
-        run_chunks<true>(a, W, s_pb, n_events, n_roads, n_hits, acc);
+        run_chunks<true>(a, W, s_pb, n_events, n_roads, n_hits, cr, ro_first, acc);
     else
-        run_chunks<false>(a, W, s_pb, n_events, n_roads, n_hits, acc);
+        run_chunks<false>(a, W, s_pb, n_events, n_roads, n_hits, cr, ro_first, acc);
 
     // block sums -> host-mapped partials (the host reduces them)
     const int lane = tid & 63, wid = tid >> 6;

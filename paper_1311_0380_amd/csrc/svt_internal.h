@@ -13,23 +13,27 @@ constexpr int kRowCap = 2048;      // (i0, i1) rows per sub-chunk
 constexpr int kMaxEventsPerChunk = 256;
 constexpr int kMaxBlocksPerCu = 16;
 constexpr int kTargetRoadsPerChunk = 256;
-// Per sector, in dynamic LDS (stride kCstStride doubles = 256 bytes):
+// Per sector, in dynamic LDS (stride kCstStride doubles = 272 bytes, an odd
+// multiple of 16 so that per-lane 16-byte reads of different sectors spread
+// over the LDS banks):
 //   doubles [0, 18)   constraint rows 3..5, 6 columns x 3 rows ([col * 3 + row])
 //   int32   [36, 39)  offsets of rows 3..5
 //   int32   [40, 58)  parameter rows 0..2, 6 columns x 3 rows ([col * 3 + row])
 //   int32   [58, 61)  offsets of rows 0..2
 constexpr int kCstDoubles = 18;
-constexpr int kCstStride = 32;
+constexpr int kCstStride = 34;
 constexpr int kCstBytesPerSector = kCstStride * 8;
 constexpr int kCstIntB = 36;      // int32 index of the constraint offsets
 constexpr int kCstIntP = 40;      // int32 index of the parameter columns
 constexpr int kCstIntPB = 58;     // int32 index of the parameter offsets
 
 // Sector tables of the wave kernel, built by svt_load_constants:
-//   pb   [n_sectors][12] fp64  columns 0..3 of constraint rows 3..5, [col * 3 + row]
+//   pb   [n_sectors][14] fp64  columns 0..3 of constraint rows 3..5, [col * 3 + row],
+//                              2 pad (112-byte stride: sectors of a wavefront's
+//                              16-byte LDS reads spread over all 8 bank groups)
 //   base [n_sectors][12] fp64  A[3..5][4], A[3..5][5], b[3..5], 3 zeros
 //   par  [n_sectors][24] int32 row k of 0..2 at [k * 8]: A[k][0..5], b[k], 0
-constexpr int kCstPbStride = 12;
+constexpr int kCstPbStride = 14;
 constexpr int kCstBaseStride = 12;
 constexpr int kCstParStride = 24;
 constexpr int kCstWaveBytes = (kCstPbStride + kCstBaseStride) * 8 + kCstParStride * 4;
