@@ -118,9 +118,9 @@ typedef struct {
                                command (copies included)                          */
 } svt_summary;
 
-/* Launch shape of the fit.  Kernel 0 (default) gives each wavefront its own
- * chunk of events (at most 63 events per chunk; it aims for 64 roads);
- * kernel 1 gives each block a chunk (it aims for 256 roads).  Results are the
+/* Launch shape of the fit.  Kernel 1 (the default) gives each block a chunk
+ * of events and aims for 256 roads per chunk; kernel 2 gives each wavefront
+ * its own chunk (at most 63 events; it aims for 64 roads).  Results are the
  * same bit for bit either way. */
 typedef struct {
     int32_t events_per_chunk;  /* events per work item (1..256); 0 = automatic    */
@@ -128,7 +128,8 @@ typedef struct {
                                   there are fewer chunks; 0 = automatic           */
     int32_t schedule;          /* 1 = cyclic (item w -> worker w mod workers),
                                   2 = blocked; 0 keeps the current value          */
-    int32_t kernel;            /* 0 = wavefront per chunk, 1 = block per chunk    */
+    int32_t kernel;            /* 0 = automatic (1), 1 = block per chunk,
+                                  2 = wavefront per chunk                         */
 } svt_tuning;
 
 /*

@@ -29,21 +29,31 @@ namespace {
 constexpr int kBins = 17 * 17;   // (n2, n3) in 0..16 x 0..16
 constexpr int kWaves = kBlock / 64;
 
-__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t x, int lane)
+// Inclusive scans across the wavefront: of two packed 32-bit counters
+// (neither half may overflow), and of one 64-bit value.
+__device__ __forceinline__ uint64_t wave_incl_scan_pair(uint64_t x)
 {
+    const uint32_t lo = wave_incl_scan((uint32_t)x), hi = wave_incl_scan((uint32_t)(x >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x)
+{
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        uint64_t t = __shfl_up(x, off, 64);
+        const uint64_t t = __shfl_up(x, off, 64);
         if (lane >= off) x += t;
     }
     return x;
 }
 
-// Block-wide exclusive scan of a value holding two packed 32-bit counters.
+// Block-wide exclusive scan: of packed 32-bit pairs (PAIR) or of 64-bit values.
+template <bool PAIR>
 __device__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_warp, uint64_t &total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint64_t incl = wave_incl_scan(v, lane);
+    uint64_t incl = PAIR ? wave_incl_scan_pair(v) : wave_incl_scan64(v);
     if (lane == 63) s_warp[wid] = incl;
     __syncthreads();
     uint64_t before = 0, tot = 0;
@@ -68,6 +78,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
+// Sums of a wavefront, kept as uniform values (wave reductions at the end of
+// every sub-chunk keep them out of the per-lane registers).
 struct Acc {
     uint64_t comb = 0, pass = 0;
     uint32_t tracks = 0;
@@ -133,12 +145,12 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
     ok = ok && h0 >= 0 && h1 <= n_hits && (int64_t)h1 - (int64_t)h0 == (int64_t)sum;
     ok = ok && (r != 0 || h0 == 0) && (r != n_roads - 1 || h1 == n_hits);
     ok = ok && xa >= 0 && xa < 4096 && xb >= 0 && xb < 4096;
-    if (inr && !ok) acc.err_road = min(acc.err_road, (uint32_t)r);
+    acc.err_road = min(acc.err_road, wave_min(inr && !ok ? (uint32_t)r : 0xFFFFFFFFu));
 
     const uint32_t nh = ok ? sum : 0u;
     const uint32_t rows = (ok && n2 * n3 > 0) ? n0 * n1 : 0u;
     uint64_t total;
-    const uint64_t ex = block_excl_scan((uint64_t)nh | ((uint64_t)rows << 32), S.warp, total);
+    const uint64_t ex = block_excl_scan<true>((uint64_t)nh | ((uint64_t)rows << 32), S.warp, total);
     const uint32_t hb = (uint32_t)ex, rbase = (uint32_t)(ex >> 32);
     const bool fits = inr && hb + nh <= (uint32_t)kHitCap && rbase + rows <= (uint32_t)kRowCap;
     const int L = __syncthreads_count(fits);
@@ -188,14 +200,16 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         S.hit[t] = h;
         if (h < 0 || h >= 4096) bad_t = min(bad_t, t);
     }
+    uint32_t bad_hit_road = 0xFFFFFFFFu;
     if (bad_t != INT32_MAX) {
         int lo = 0, hi = L;     // last road with hb <= bad_t
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if ((int32_t)S.hb[mid] <= bad_t) lo = mid; else hi = mid;
         }
-        acc.err_road = min(acc.err_road, (uint32_t)(s + lo));
+        bad_hit_road = (uint32_t)(s + lo);
     }
+    acc.err_road = min(acc.err_road, wave_min(bad_hit_road));
     // bin starts: exclusive scan of the 289 bins by wave 0
     if (tid < 64) {
         uint32_t vb[5], loc = 0;
@@ -205,8 +219,8 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
             vb[q] = b < kBins ? S.bin[b] : 0u;
             loc += vb[q];
         }
-        const uint64_t incl = wave_incl_scan(loc, tid);
-        uint32_t run = (uint32_t)incl - loc;
+        const uint32_t incl = wave_incl_scan(loc);
+        uint32_t run = incl - loc;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const int b = tid * 5 + q;
@@ -272,11 +286,18 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
     }
     __syncthreads();
 
-    // C: results of each road
+    // C: results of each road.  Its counts, hit base and sector come back
+    // from LDS (zero counts for a malformed road give the same outputs as
+    // the road's error path), which keeps phase A's values out of phase B.
+    uint32_t my_comb = 0, my_pass = 0, my_track = 0;
     if (active) {
+        const uint32_t c4 = S.n4[tid], hb = S.hb[tid], sec = S.sec[tid];
+        const uint32_t n0 = c4 & 255u, n1 = (c4 >> 8) & 255u, n2 = (c4 >> 16) & 255u,
+                       n3 = c4 >> 24;
+        const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
         const unsigned long long key = S.key[tid];
         const uint32_t np = S.np[tid];
-        const bool found = ok && key != ~0ull;
+        const bool found = key != ~0ull;
         int32_t bk = -1;
         uint64_t c2 = ~0ull;
         int32_t p[3] = {0, 0, 0};
@@ -303,8 +324,8 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
                 p[k] = (int32_t)acc32;
             }
         }
-        a.ncomb[r] = ok ? (int32_t)(n0 * n1 * n2 * n3) : 0;
-        a.npass[r] = ok ? (int32_t)np : 0;
+        a.ncomb[r] = (int32_t)(n0 * n1 * n2 * n3);
+        a.npass[r] = (int32_t)np;
         a.best[r] = bk;
         a.chi2[r] = c2;
         a.params[3 * (int64_t)r + 0] = p[0];
@@ -319,12 +340,13 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
             }
             atomicAdd(&S.evcnt[lo], 1u);
         }
-        if (ok) {
-            acc.comb += n0 * n1 * n2 * n3;
-            acc.pass += np;
-            acc.tracks += found ? 1u : 0u;
-        }
+        my_comb = n0 * n1 * n2 * n3;
+        my_pass = np;
+        my_track = found ? 1u : 0u;
     }
+    acc.comb += wave_sum(my_comb);      // each at most 64 * 2^16
+    acc.pass += wave_sum(my_pass);
+    acc.tracks += wave_sum(my_track);
     __syncthreads();
     return L;
 }
@@ -364,6 +386,22 @@ fit_kernel(FitArgs a)
     const int32_t n_sectors = a.n_sectors;
     double *s_cd = reinterpret_cast<double *>(s_dyn);
 
+    Acc acc;
+    const double cut = a.cut_d;
+    const int32_t E = a.events_per_chunk;
+    const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
+    int32_t c_first, c_step, c_last;
+    chunk_range(n_chunks, a.schedule, c_first, c_step, c_last);
+
+    // the first chunk's event boundaries are in flight while the sector
+    // constants are staged
+    int32_t ev0 = 0, ev1 = 0;
+    if (c_first < c_last) {
+        const int32_t e0 = c_first * E, ne = min(E, n_events - e0);
+        if (tid <= ne) ev0 = a.road_offsets[e0 + tid];
+        if (tid + kBlock <= ne) ev1 = a.road_offsets[e0 + tid + kBlock];
+    }
+
     // sector constants -> LDS: constraint rows 3..5 as fp64 columns, their
     // offsets as int32; parameter rows 0..2 and offsets as int32
     for (int i = tid; i < n_sectors * 6; i += kBlock) {
@@ -384,50 +422,42 @@ fit_kernel(FitArgs a)
         }
     }
     for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;
-    __syncthreads();
 
-    Acc acc;
-    const double cut = a.cut_d;
-    const int32_t E = a.events_per_chunk;
-    const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
-
-    int32_t c_first, c_step, c_last;
-    chunk_range(n_chunks, a.schedule, c_first, c_step, c_last);
+    if (c_first < c_last) {
+        const int32_t ne = min(E, n_events - c_first * E);
+        if (tid <= ne) S.evro[tid] = ev0;
+        if (tid + kBlock <= ne) S.evro[tid + kBlock] = ev1;
+    }
     for (int32_t c = c_first; c < c_last; c += c_step) {
         const int32_t e0 = c * E;
         const int32_t ne = min(E, n_events - e0);
-        const int32_t ra = clampi(a.road_offsets[e0], 0, n_roads);
-        const int32_t rb = clampi(a.road_offsets[e0 + ne], ra, n_roads);
-        for (int i = tid; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
+        if (c != c_first)
+            for (int i = tid; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
         for (int i = tid; i < ne; i += kBlock) S.evcnt[i] = 0;
         __syncthreads();
+        const int32_t ra = clampi(S.evro[0], 0, n_roads);
+        const int32_t rb = clampi(S.evro[ne], ra, n_roads);
         for (int32_t s = ra; s < rb;)
             s += a.frac_key ? process_sub<true>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc)
                             : process_sub<false>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc);
+        uint32_t bad_event = 0xFFFFFFFFu;
         for (int i = tid; i < ne; i += kBlock) {
             const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
             const bool bad = lo < 0 || hi < lo || hi > n_roads || (e == 0 && lo != 0) ||
                              (e == n_events - 1 && hi != n_roads);
-            if (bad) acc.err_event = min(acc.err_event, (uint32_t)e);
+            if (bad) bad_event = min(bad_event, (uint32_t)e);
             a.ntracks[e] = (int32_t)S.evcnt[i];
         }
+        acc.err_event = min(acc.err_event, wave_min(bad_event));
         __syncthreads();
     }
 
-    // block sums -> host-mapped partials (the host reduces them)
+    // block sums -> host-mapped partials (the host reduces them); the
+    // wavefront sums are uniform already
     const int lane = tid & 63, wid = tid >> 6;
-    uint64_t comb = acc.comb, pass = acc.pass;
-    uint32_t trk = acc.tracks, er = acc.err_road, ee = acc.err_event;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        comb += __shfl_xor(comb, off, 64);
-        pass += __shfl_xor(pass, off, 64);
-        trk += __shfl_xor(trk, off, 64);
-        er = min(er, (uint32_t)__shfl_xor(er, off, 64));
-        ee = min(ee, (uint32_t)__shfl_xor(ee, off, 64));
-    }
     __shared__ BlockPartial s_part[kWaves];
-    if (lane == 0) s_part[wid] = BlockPartial{comb, pass, trk, er, ee, 0};
+    if (lane == 0)
+        s_part[wid] = BlockPartial{acc.comb, acc.pass, acc.tracks, acc.err_road, acc.err_event, 0};
     __syncthreads();
     if (tid == 0) {
         BlockPartial p = s_part[0];
@@ -476,7 +506,7 @@ __global__ void __launch_bounds__(kBlock) scan_tile_sums(int64_t *tile_sum, int3
         const int32_t b = b0 + threadIdx.x;
         const int64_t v = b < n_tiles ? tile_sum[b] : 0;
         uint64_t tot;
-        const int64_t ex = (int64_t)block_excl_scan((uint64_t)v, warp, tot);
+        const int64_t ex = (int64_t)block_excl_scan<false>((uint64_t)v, warp, tot);
         if (b < n_tiles) tile_sum[b] = carry + ex;
         carry += (int64_t)tot;
     }
@@ -493,7 +523,7 @@ __global__ void __launch_bounds__(kBlock) scan_apply(const int32_t *ncomb, int32
         const int64_t g = base + i0 + threadIdx.x;
         const int64_t v = g < n ? ncomb[g] : 0;
         uint64_t tot;
-        const int64_t ex = (int64_t)block_excl_scan((uint64_t)v, warp, tot);
+        const int64_t ex = (int64_t)block_excl_scan<false>((uint64_t)v, warp, tot);
         if (g < n) out[g] = carry + ex;
         carry += (int64_t)tot;
     }

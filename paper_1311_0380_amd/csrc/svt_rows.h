@@ -48,6 +48,30 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
     return x;
 }
 
+// Sum and minimum across the wavefront (all lanes active), as uniform values.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x)
+{
+    return __builtin_amdgcn_readlane(wave_incl_scan(x), 63);
+}
+
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp_or_max(uint32_t x)
+{
+    // lanes without a source keep 0xFFFFFFFF, the identity of min
+    return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, Ctrl, RowMask, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t x)
+{
+    x = min(x, dpp_or_max<kRowShr + 1, 0xF>(x));
+    x = min(x, dpp_or_max<kRowShr + 2, 0xF>(x));
+    x = min(x, dpp_or_max<kRowShr + 4, 0xF>(x));
+    x = min(x, dpp_or_max<kRowShr + 8, 0xF>(x));
+    x = min(x, dpp_or_max<kRowBcast15, 0xA>(x));
+    x = min(x, dpp_or_max<kRowBcast31, 0xC>(x));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
 // Maximum across the wavefront (all lanes active), as a uniform value.
 __device__ __forceinline__ uint32_t wave_max(uint32_t x)
 {
@@ -126,6 +150,9 @@ __device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t
                 st.best = dmin(st.best, v);
             }
         }
+        // keep the scheduler from interleaving all N2 * N3 combinations,
+        // which would cost more registers than it gains
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 

@@ -83,7 +83,7 @@ struct svt_ctx {
     DevBuf shadow_scratch;                   // float-shadow partial sums
     std::vector<DevBuf> pool;                // idle staging buffers
     uint64_t const_gen = 0;                  // bumped by every svt_load_constants
-    svt_tuning tuning{0, 0, 1, 0};  // automatic chunk and occupancy, cyclic, wave kernel
+    svt_tuning tuning{0, 0, 1, 0};  // automatic chunk, occupancy and kernel; cyclic
 };
 
 // A captured fit of any batch up to a fixed capacity (see svt_plan_create).
@@ -227,7 +227,7 @@ int auto_events_per_chunk(int32_t n_events, int32_t n_roads, int target, int max
 // grid (graph plans) keeps the full size; otherwise the grid shrinks to the
 // number of chunks.
 struct LaunchShape {
-    int kernel;   // 0 wave, 1 block
+    int kernel;   // 1 block per chunk, 2 wavefront per chunk
     int epc;      // events per chunk
     int grid;
 };
@@ -236,10 +236,10 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
                          bool persistent)
 {
     LaunchShape ls;
-    ls.kernel = t.kernel == 1 ? 1 : 0;
+    ls.kernel = t.kernel == 2 ? 2 : 1;
     int bpc;
     int64_t per_block;
-    if (ls.kernel == 0) {
+    if (ls.kernel == 2) {
         ls.epc = t.events_per_chunk > 0
                      ? (t.events_per_chunk < svt::kWaveMaxEvents ? t.events_per_chunk
                                                                  : svt::kWaveMaxEvents)
@@ -275,7 +275,7 @@ hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &l
         w + (size_t)256 * (svt::kCstPbStride + svt::kCstBaseStride) * 8);
     a.frac_key = c->cut < (1ull << 44) ? 1 : 0;
     a.events_per_chunk = ls.epc;
-    if (ls.kernel == 0) return svt::launch_fit_wave(a, ls.grid, st);
+    if (ls.kernel == 2) return svt::launch_fit_wave(a, ls.grid, st);
     return svt::launch_fit(a, ls.grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
 }
 
@@ -468,7 +468,7 @@ svt_status svt_set_tuning(svt_ctx *c, const svt_tuning *t)
     if (t->events_per_chunk < 0 || t->events_per_chunk > svt::kMaxEventsPerChunk) return SVT_E_INVAL;
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > svt::kMaxBlocksPerCu) return SVT_E_INVAL;
     if (t->schedule < 0 || t->schedule > 2) return SVT_E_INVAL;
-    if (t->kernel < 0 || t->kernel > 1) return SVT_E_INVAL;
+    if (t->kernel < 0 || t->kernel > 2) return SVT_E_INVAL;
     c->tuning.events_per_chunk = t->events_per_chunk;   // 0 = automatic
     c->tuning.blocks_per_cu = t->blocks_per_cu;         // 0 = automatic
     if (t->schedule) c->tuning.schedule = t->schedule;
@@ -838,7 +838,7 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
         if (tuning->events_per_chunk < 0 || tuning->events_per_chunk > svt::kMaxEventsPerChunk ||
             tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > svt::kMaxBlocksPerCu ||
             tuning->schedule < 0 || tuning->schedule > 2 || tuning->kernel < 0 ||
-            tuning->kernel > 1) {
+            tuning->kernel > 2) {
             delete p;
             return SVT_E_INVAL;
         }

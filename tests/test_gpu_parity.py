@@ -151,12 +151,12 @@ def restore_tuning(ctx):
 
 
 @pytest.mark.parametrize("tuning", [
-    # wavefront per chunk (the default kernel); 256 events per chunk clamps to 63
-    dict(events_per_chunk=1), dict(events_per_chunk=7), dict(events_per_chunk=63),
-    dict(events_per_chunk=256), dict(blocks_per_cu=1, schedule=1),
-    dict(blocks_per_cu=4, schedule=1), dict(blocks_per_cu=8, schedule=2),
-    dict(events_per_chunk=3, schedule=2),
-    # block per chunk
+    # wavefront per chunk; 256 events per chunk clamps to 63
+    dict(kernel=2), dict(kernel=2, events_per_chunk=1), dict(kernel=2, events_per_chunk=7),
+    dict(kernel=2, events_per_chunk=63), dict(kernel=2, events_per_chunk=256),
+    dict(kernel=2, blocks_per_cu=1, schedule=1), dict(kernel=2, blocks_per_cu=4, schedule=1),
+    dict(kernel=2, blocks_per_cu=8, schedule=2), dict(kernel=2, events_per_chunk=3, schedule=2),
+    # block per chunk (the default)
     dict(kernel=1), dict(kernel=1, events_per_chunk=1), dict(kernel=1, events_per_chunk=7),
     dict(kernel=1, events_per_chunk=256), dict(kernel=1, blocks_per_cu=1, schedule=1),
     dict(kernel=1, blocks_per_cu=3, schedule=1), dict(kernel=1, blocks_per_cu=8, schedule=2),
@@ -171,7 +171,7 @@ def test_launch_shapes_same_bits(ctx, oracle_lib, tuning):
         restore_tuning(ctx)
 
 
-@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("cut", [1 << 32, (1 << 44) - 1, 1 << 44, (1 << 48) - 1])
 def test_cut_forms_and_deep_layers(ctx, oracle_lib, kernel, cut):
     """Up to 16 hits per layer (every inner trip count 1..16, rows of up to
