@@ -402,24 +402,12 @@ fit_kernel(FitArgs a)
         if (tid + kBlock <= ne) ev1 = a.road_offsets[e0 + tid + kBlock];
     }
 
-    // sector constants -> LDS: constraint rows 3..5 as fp64 columns, their
-    // offsets as int32; parameter rows 0..2 and offsets as int32
-    for (int i = tid; i < n_sectors * 6; i += kBlock) {
-        const int sct = i / 6, col = i - sct * 6;
-        int32_t *ci = reinterpret_cast<int32_t *>(s_cd + sct * kCstStride);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            s_cd[sct * kCstStride + col * 3 + k] = (double)a.coef[(sct * 6 + 3 + k) * 6 + col];
-            ci[kCstIntP + col * 3 + k] = a.coef[(sct * 6 + k) * 6 + col];
-        }
-    }
-    for (int sct = tid; sct < n_sectors; sct += kBlock) {
-        int32_t *ci = reinterpret_cast<int32_t *>(s_cd + sct * kCstStride);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            ci[kCstIntB + k] = a.offset[sct * 6 + 3 + k];
-            ci[kCstIntPB + k] = a.offset[sct * 6 + k];
-        }
+    // sector constants -> LDS: a copy of the image built at load time
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.cst_block);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_cd);
+        const int n16 = n_sectors * kCstBytesPerSector / 16;
+        for (int i = tid; i < n16; i += kBlock) dst[i] = src[i];
     }
     for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;
 

@@ -83,6 +83,7 @@ struct FitArgs {
     int32_t *params;
     uint32_t *hit_index4;       // 4 x uint8 per road
     int32_t *ntracks;
+    const double *cst_block;    // block-kernel LDS image: [n_sectors][kCstStride]
     const double *cst_pb;       // wave-kernel sector tables (device)
     const double *cst_base;
     const int32_t *cst_par;

@@ -74,6 +74,7 @@ struct svt_ctx {
     int32_t *coef = nullptr;
     int32_t *offset = nullptr;
     void *cst_wave = nullptr;                // sector tables of the wave kernel
+    void *cst_block = nullptr;               // LDS image of the block kernel's table
     int32_t n_sectors = 0;
     uint64_t cut = 0;
     bool loaded = false;
@@ -274,6 +275,7 @@ hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &l
     a.cst_par = reinterpret_cast<const int32_t *>(
         w + (size_t)256 * (svt::kCstPbStride + svt::kCstBaseStride) * 8);
     a.frac_key = c->cut < (1ull << 44) ? 1 : 0;
+    a.cst_block = static_cast<const double *>(c->cst_block);
     a.events_per_chunk = ls.epc;
     if (ls.kernel == 2) return svt::launch_fit_wave(a, ls.grid, st);
     return svt::launch_fit(a, ls.grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
@@ -395,6 +397,7 @@ svt_status svt_destroy(svt_ctx *c)
     }
     if (c->coef) (void)hipFree(c->coef);
     if (c->cst_wave) (void)hipFree(c->cst_wave);
+    if (c->cst_block) (void)hipFree(c->cst_block);
     if (c->shadow_scratch.ptr) (void)hipFree(c->shadow_scratch.ptr);
     for (DevBuf &b : c->pool) (void)hipFree(b.ptr);
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -428,6 +431,10 @@ svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef
         svt_status st = dev_alloc(c, &c->cst_wave, (size_t)256 * svt::kCstWaveBytes);
         if (st != SVT_OK) return st;
     }
+    if (c->cst_block == nullptr) {
+        svt_status st = dev_alloc(c, &c->cst_block, (size_t)256 * svt::kCstBytesPerSector);
+        if (st != SVT_OK) return st;
+    }
     HIP_TRY(hipMemcpy(c->coef, coef, sizeof(int32_t) * 36 * n_sectors, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->offset, offset, sizeof(int32_t) * 6 * n_sectors, hipMemcpyHostToDevice));
     {
@@ -449,6 +456,23 @@ svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef
                 par[(size_t)s * svt::kCstParStride + k * 8 + 6] = b[k];
             }
         }
+        // the block kernel's LDS image (see svt_internal.h for the layout)
+        std::vector<double> img((size_t)n_sectors * svt::kCstStride, 0.0);
+        for (int s = 0; s < n_sectors; ++s) {
+            const int32_t *A = coef + s * 36, *b = offset + s * 6;
+            double *d = img.data() + (size_t)s * svt::kCstStride;
+            int32_t *ci = reinterpret_cast<int32_t *>(d);
+            for (int col = 0; col < 6; ++col)
+                for (int k = 0; k < 3; ++k) {
+                    d[col * 3 + k] = (double)A[(3 + k) * 6 + col];
+                    ci[svt::kCstIntP + col * 3 + k] = A[k * 6 + col];
+                }
+            for (int k = 0; k < 3; ++k) {
+                ci[svt::kCstIntB + k] = b[3 + k];
+                ci[svt::kCstIntPB + k] = b[k];
+            }
+        }
+        HIP_TRY(hipMemcpy(c->cst_block, img.data(), img.size() * 8, hipMemcpyHostToDevice));
         char *w = static_cast<char *>(c->cst_wave);
         HIP_TRY(hipMemcpy(w, pb.data(), pb.size() * 8, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(w + pb.size() * 8, bs.data(), bs.size() * 8, hipMemcpyHostToDevice));
