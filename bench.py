@@ -42,7 +42,7 @@ def algorithmic_bytes(n_events, n_roads, n_hits, n_sectors=72):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("svt_fit.hip", "svt_internal.h"):
+    for f in ("svt_fit.hip", "svt_rows.h", "svt_internal.h"):
         with open(os.path.join(ROOT, "paper_1311_0380_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
