@@ -268,19 +268,8 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         st.np = 0;
         run_row<F>(st, S.hit, p2, rn2, rn3, F ? cut + 0.5 : cut);
         if (act) {
-            bool found;
-            unsigned long long c2;
-            uint32_t bidx;
-            if constexpr (F) {
-                found = st.best < cut + 1.0;
-                c2 = (unsigned long long)st.best;                       // floor: best >= 0
-                bidx = (uint32_t)((st.best - (double)c2) * 256.0);      // exact: a multiple of 2^-8
-            } else {
-                found = st.bidx != 0xFFFFFFFFu;
-                c2 = (unsigned long long)st.best;
-                bidx = st.bidx;
-            }
-            if (found) atomicMin(&S.key[j], (c2 << 16) | (i0 << 12) | (i1 << 8) | bidx);
+            unsigned long long key;
+            if (row_key<F>(st, cut, i0, i1, key)) atomicMin(&S.key[j], key);
             if (st.np) atomicAdd(&S.np[j], st.np);
         }
     }

@@ -116,6 +116,26 @@ __device__ __forceinline__ double dmin(double a, double b)
     return r;
 }
 
+// The road key of a row's best, chi2 << 16 | i0 << 12 | i1 << 8 | i2 << 4 | i3,
+// and whether the row has a passing combination.  In the fraction form
+// 256 * best = 256 chi2 + (i2 * 16 + i3) is an integer below 2^52, which
+// fma(best, 256, 2^52) places in the low mantissa bits exactly.
+template <bool F>
+__device__ __forceinline__ bool row_key(const Row &st, double cut, uint32_t i0, uint32_t i1,
+                                        unsigned long long &key)
+{
+    if constexpr (F) {
+        const double t = fma(st.best, 256.0, 0x1p52);
+        const unsigned long long k =
+            (unsigned long long)__double_as_longlong(t) & 0x000FFFFFFFFFFFFFull;
+        key = ((k >> 8) << 16) | (i0 << 12) | (i1 << 8) | (k & 255u);
+        return st.best < cut + 1.0;
+    } else {
+        key = ((unsigned long long)st.best << 16) | (i0 << 12) | (i1 << 8) | st.bidx;
+        return st.bidx != 0xFFFFFFFFu;
+    }
+}
+
 // Small rows, fully unrolled: N2 = the wavefront's largest n2, N3 = its n3
 // (uniform) or largest n3 (UNI false).  All hits are loaded up front (clamped
 // into the row's lists); i2 past the lane's n2 is masked off, i3 past its n3
@@ -126,12 +146,12 @@ __device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t
                                            uint32_t n3, double lim)
 {
     const uint32_t p3 = p2 + n2;
+    const uint32_t l2 = n2 - 1, l3 = n3 - 1;
     double h2[N2], h3[N3];
 #pragma unroll
-    for (int i = 0; i < N2; ++i) h2[i] = (double)hit[p2 + (i < (int)n2 ? (uint32_t)i : n2 - 1)];
+    for (int i = 0; i < N2; ++i) h2[i] = (double)hit[p2 + min((uint32_t)i, l2)];
 #pragma unroll
-    for (int i = 0; i < N3; ++i)
-        h3[i] = (double)hit[p3 + (UNI || i < (int)n3 ? (uint32_t)i : n3 - 1)];
+    for (int i = 0; i < N3; ++i) h3[i] = (double)hit[p3 + (UNI ? (uint32_t)i : min((uint32_t)i, l3))];
 #pragma unroll
     for (int i2 = 0; i2 < N2; ++i2) {
         if (i2 == 0 || (uint32_t)i2 < n2) {
