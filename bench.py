@@ -198,6 +198,7 @@ def section_serve(args, svt, synth, torch, serve):
     out = {"workload": "trigger serving: Poisson bursts of 1-3000 events (log-uniform), "
                        "events shaped as the 3000-event plain fit, pinned host pool",
            "loads": []}
+    import gc
     pool = serve.HostPool(batch)
     comb_road = np.prod(batch.nhits.astype(np.int64), axis=1)
     comb_cum = np.concatenate([[0], np.cumsum(comb_road)])[batch.road_offsets.astype(np.int64)]
@@ -212,14 +213,24 @@ def section_serve(args, svt, synth, torch, serve):
         srv.warm()                         # staging buffers for the largest launches
         srv.run(arr[:8])
         srv.launch_sizes.clear()
-        t0 = time.perf_counter()
-        recs = srv.run(arr)
-        wall = time.perf_counter() - t0
+        gc.collect()
+        gc.disable()                       # no collector pauses inside the serving loop
+        try:
+            t0 = time.perf_counter()
+            recs = srv.run(arr)
+            wall = time.perf_counter() - t0
+        finally:
+            gc.enable()
         ev = sum(r.e1 - r.e0 for r in recs)
         comb = sum(int(comb_cum[r.e1] - comb_cum[r.e0]) for r in recs)
         st_b = serve.latency_stats(recs)
         plain = serve.PlainServer(ctx, pool, window=32)
-        precs = plain.run(arr[:nb_plain], time_limit=60.0)
+        gc.collect()
+        gc.disable()
+        try:
+            precs = plain.run(arr[:nb_plain], time_limit=60.0)
+        finally:
+            gc.enable()
         st_p = serve.latency_stats(precs)
         ctx.close()
         out["loads"].append({"events_per_s": load, "bursts": len(recs),

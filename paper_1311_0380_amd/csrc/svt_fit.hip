@@ -93,7 +93,7 @@ struct Shared {
     uint32_t np[kSubRoads];                 // passing combinations of each road
     uint16_t hb[kSubRoads];                 // first staged hit of each road
     uint16_t row[kRowCap];                  // road | i0 << 8 | i1 << 12, binned by (n2, n3)
-    int16_t hit[kHitCap];                   // staged hit words
+    int16_t hit[kHitCap + 16];              // staged hit words (+ pad read by row loops)
     uint32_t bin[kBins];
     int32_t evro[kMaxEventsPerChunk + 1];
     uint32_t evcnt[kMaxEventsPerChunk];
@@ -309,7 +309,7 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
                 uint32_t acc32 = (uint32_t)ci[kCstIntPB + k];
 #pragma unroll
                 for (int col = 0; col < 6; ++col)
-                    acc32 += (uint32_t)ci[kCstIntP + col * 3 + k] * x[col];
+                    acc32 += (uint32_t)__mul24(ci[kCstIntP + col * 3 + k], (int32_t)x[col]);
                 p[k] = (int32_t)acc32;
             }
         }

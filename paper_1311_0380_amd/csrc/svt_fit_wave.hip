@@ -37,7 +37,7 @@ struct WaveLds {
     uint32_t np[kWRoads];               // passing combinations of each road
     uint32_t evcnt[kWRoads];            // tracks of each event of the chunk
     uint16_t row[kWRowCap];             // road | i0 << 6 | i1 << 10
-    int16_t hit[kWHitCap];              // staged hit words
+    int16_t hit[kWHitCap + 16];         // staged hit words (+ pad read by row loops)
 };
 
 struct Acc {
@@ -257,7 +257,8 @@ __device__ int wave_sub(const FitArgs &a, WaveLds &W, const double *s_pb, int32_
             for (int k = 0; k < 3; ++k) {
                 uint32_t acc32 = (uint32_t)ci[k * 8 + 6];
 #pragma unroll
-                for (int col = 0; col < 6; ++col) acc32 += (uint32_t)ci[k * 8 + col] * x[col];
+                for (int col = 0; col < 6; ++col)
+                    acc32 += (uint32_t)__mul24(ci[k * 8 + col], (int32_t)x[col]);
                 p[k] = (int32_t)acc32;
             }
             atomicAdd(&W.evcnt[ev], 1u);

@@ -137,19 +137,20 @@ __device__ __forceinline__ bool row_key(const Row &st, double cut, uint32_t i0, 
 }
 
 // Small rows, fully unrolled: N2 = the wavefront's largest n2, N3 = its n3
-// (uniform) or largest n3 (UNI false).  All hits are loaded up front (clamped
-// into the row's lists); i2 past the lane's n2 is masked off, i3 past its n3
-// (mixed wavefronts only) computes a duplicate with a larger fraction that
-// never wins and is kept out of the pass count.
+// (uniform) or largest n3 (UNI false).  All hits are loaded up front.  i2 past
+// the lane's n2 is masked off, so its word is read unclamped (the staged hit
+// array carries a pad of 16 words for this); i3 past the lane's n3 (mixed
+// wavefronts only) is clamped into the list, computes a duplicate with a
+// larger fraction that never wins and is kept out of the pass count.
 template <int N2, int N3, bool UNI>
 __device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
                                            uint32_t n3, double lim)
 {
     const uint32_t p3 = p2 + n2;
-    const uint32_t l2 = n2 - 1, l3 = n3 - 1;
+    const uint32_t l3 = n3 - 1;
     double h2[N2], h3[N3];
 #pragma unroll
-    for (int i = 0; i < N2; ++i) h2[i] = (double)hit[p2 + min((uint32_t)i, l2)];
+    for (int i = 0; i < N2; ++i) h2[i] = (double)hit[p2 + i];
 #pragma unroll
     for (int i = 0; i < N3; ++i) h3[i] = (double)hit[p3 + (UNI ? (uint32_t)i : min((uint32_t)i, l3))];
 #pragma unroll
