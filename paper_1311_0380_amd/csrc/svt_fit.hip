@@ -313,14 +313,16 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
                 p[k] = (int32_t)acc32;
             }
         }
-        a.ncomb[r] = (int32_t)(n0 * n1 * n2 * n3);
-        a.npass[r] = (int32_t)np;
-        a.best[r] = bk;
-        a.chi2[r] = c2;
-        a.params[3 * (int64_t)r + 0] = p[0];
-        a.params[3 * (int64_t)r + 1] = p[1];
-        a.params[3 * (int64_t)r + 2] = p[2];
-        a.hit_index4[r] = hi4;
+        // results are written once and not read again by this kernel:
+        // streaming stores keep them from filling (and later flushing) L2
+        __builtin_nontemporal_store((int32_t)(n0 * n1 * n2 * n3), &a.ncomb[r]);
+        __builtin_nontemporal_store((int32_t)np, &a.npass[r]);
+        __builtin_nontemporal_store(bk, &a.best[r]);
+        __builtin_nontemporal_store(c2, &a.chi2[r]);
+        __builtin_nontemporal_store(p[0], &a.params[3 * (int64_t)r + 0]);
+        __builtin_nontemporal_store(p[1], &a.params[3 * (int64_t)r + 1]);
+        __builtin_nontemporal_store(p[2], &a.params[3 * (int64_t)r + 2]);
+        __builtin_nontemporal_store(hi4, &a.hit_index4[r]);
         if (found) {
             int lo = 0, hi = ne;   // events [lo, hi): largest e with evro[e] <= r
             while (hi - lo > 1) {

@@ -263,14 +263,15 @@ __device__ int wave_sub(const FitArgs &a, WaveLds &W, const double *s_pb, int32_
             }
             atomicAdd(&W.evcnt[ev], 1u);
         }
-        a.ncomb[r] = (int32_t)(n0 * n1 * n2 * n3);
-        a.npass[r] = (int32_t)np;
-        a.best[r] = bk;
-        a.chi2[r] = c2;
-        a.params[3 * (int64_t)r + 0] = p[0];
-        a.params[3 * (int64_t)r + 1] = p[1];
-        a.params[3 * (int64_t)r + 2] = p[2];
-        a.hit_index4[r] = hi4;
+        // written once, never read back here: streaming stores
+        __builtin_nontemporal_store((int32_t)(n0 * n1 * n2 * n3), &a.ncomb[r]);
+        __builtin_nontemporal_store((int32_t)np, &a.npass[r]);
+        __builtin_nontemporal_store(bk, &a.best[r]);
+        __builtin_nontemporal_store(c2, &a.chi2[r]);
+        __builtin_nontemporal_store(p[0], &a.params[3 * (int64_t)r + 0]);
+        __builtin_nontemporal_store(p[1], &a.params[3 * (int64_t)r + 1]);
+        __builtin_nontemporal_store(p[2], &a.params[3 * (int64_t)r + 2]);
+        __builtin_nontemporal_store(hi4, &a.hit_index4[r]);
         acc.comb += n0 * n1 * n2 * n3;
         acc.pass += np;
         acc.tracks += found ? 1u : 0u;
