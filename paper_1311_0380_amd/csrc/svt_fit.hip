@@ -68,16 +68,6 @@ __device__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_warp, uint64_t &tota
     return before + incl - v;
 }
 
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        uint32_t t = __shfl_xor(v, off, 64);
-        v = v > t ? v : t;
-    }
-    return v;
-}
-
 // Sums of a wavefront, kept as uniform values (wave reductions at the end of
 // every sub-chunk keep them out of the per-lane registers).
 struct Acc {

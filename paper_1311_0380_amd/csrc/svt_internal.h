@@ -20,7 +20,6 @@ constexpr int kTargetRoadsPerChunk = 256;
 //   int32   [36, 39)  offsets of rows 3..5
 //   int32   [40, 58)  parameter rows 0..2, 6 columns x 3 rows ([col * 3 + row])
 //   int32   [58, 61)  offsets of rows 0..2
-constexpr int kCstDoubles = 18;
 constexpr int kCstStride = 34;
 constexpr int kCstBytesPerSector = kCstStride * 8;
 constexpr int kCstIntB = 36;      // int32 index of the constraint offsets
