@@ -42,3 +42,38 @@ def test_status_strings():
     from paper_1311_0380_amd import svt
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert svt.svt_status_string(code).startswith("SVT_")
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the size and field offsets the
+    C compiler gives it from include/svt.h (host compiler, no GPU)."""
+    import shutil
+    import subprocess
+    from paper_1311_0380_amd import svt
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"svt_event_batch": svt.svt_event_batch, "svt_results": svt.svt_results,
+               "svt_summary": svt.svt_summary, "svt_tuning": svt.svt_tuning,
+               "svt_device_info": svt.svt_device_info,
+               "svt_shadow_tracks": svt.svt_shadow_tracks}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "svt.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)

@@ -1,0 +1,66 @@
+"""Host-side logic that needs no GPU: the autotuner's candidate set, the
+workload signature, and how bench.py ties HBM traffic to the profiled
+kernel source."""
+import os
+
+import pytest
+
+from paper_1311_0380_amd import synth
+
+
+def uneven():
+    # the module imports torch and the binding only for device work
+    from paper_1311_0380_amd import uneven as u
+    return u
+
+
+@pytest.mark.parametrize("ne,nr", [(10000, 160000), (3000, 192000), (100, 800), (1, 5000),
+                                   (50000, 50000), (7, 7000)])
+def test_candidates_are_valid_shapes(ne, nr):
+    cands = uneven().candidates(ne, nr)
+    assert cands
+    for c in cands:
+        assert c["kernel"] in (1, 2)
+        assert 1 <= c["events_per_chunk"] <= 256 or c["events_per_chunk"] == 0
+        if c["kernel"] == 2:
+            assert c["events_per_chunk"] <= 63
+        assert 0 <= c["blocks_per_cu"] <= 16
+        assert c["schedule"] in (1, 2)
+
+
+def test_candidates_cover_both_kernels_on_the_uneven_workload():
+    cands = uneven().candidates(10000, 160000)
+    assert {c["kernel"] for c in cands} == {1, 2}
+
+
+def test_workload_signature_groups_similar_batches():
+    u = uneven()
+    a = u.workload_signature(10000, 160000, 1100000)
+    b = u.workload_signature(10001, 160100, 1100500)
+    c = u.workload_signature(3000, 192000, 1920000)
+    assert a == b and a != c
+
+
+def test_traffic_follows_the_profiled_source(tmp_path, monkeypatch):
+    import bench
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "fit_kernel_3000ev_hbm_counters.md").write_text(
+        "| x | 1 |\n"
+        f"kernel_sha256_prefix = {bench.kernel_source_hash()}\n"
+        "traffic_bytes_per_launch = 12345\n")
+    src = os.path.join(bench.ROOT, "paper_1311_0380_amd")
+    (tmp_path / "paper_1311_0380_amd").symlink_to(src)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic() == 12345
+    (prof / "fit_kernel_3000ev_hbm_counters.md").write_text(
+        "kernel_sha256_prefix = 0000000000000000\ntraffic_bytes_per_launch = 12345\n")
+    assert bench.measured_traffic() is None
+    (prof / "fit_kernel_3000ev_hbm_counters.md").unlink()
+    assert bench.measured_traffic() is None
+
+
+def test_algorithmic_bytes_of_the_headline_batch():
+    import bench
+    b, _ = synth.cfg2()
+    assert bench.algorithmic_bytes(b.n_events, b.n_roads, b.n_hits) == 13284326
