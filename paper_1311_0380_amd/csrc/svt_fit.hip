@@ -88,6 +88,7 @@ struct Shared {
     int32_t evro[kMaxEventsPerChunk + 1];
     uint32_t evcnt[kMaxEventsPerChunk];
     uint64_t warp[kWaves];
+    uint32_t fitc[kWaves];
     uint8_t sec[kSubRoads];
     int32_t misc[4];
 };
@@ -139,11 +140,25 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
 
     const uint32_t nh = ok ? sum : 0u;
     const uint32_t rows = (ok && n2 * n3 > 0) ? n0 * n1 : 0u;
-    uint64_t total;
-    const uint64_t ex = block_excl_scan<true>((uint64_t)nh | ((uint64_t)rows << 32), S.warp, total);
+    // block scan of (hits, rows); the roads that fit are a prefix of the
+    // block, counted per wave and summed across the scan's second barrier
+    const uint64_t pk = (uint64_t)nh | ((uint64_t)rows << 32);
+    const uint64_t incl = wave_incl_scan_pair(pk);
+    const int lane = tid & 63, wid = tid >> 6;
+    if (lane == 63) S.warp[wid] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) before += (w < wid) ? S.warp[w] : 0ull;
+    const uint64_t ex = before + incl - pk;
     const uint32_t hb = (uint32_t)ex, rbase = (uint32_t)(ex >> 32);
     const bool fits = inr && hb + nh <= (uint32_t)kHitCap && rbase + rows <= (uint32_t)kRowCap;
-    const int L = __syncthreads_count(fits);
+    const uint32_t wfit = (uint32_t)__popcll(__ballot(fits));
+    if (lane == 0) S.fitc[wid] = wfit;
+    __syncthreads();
+    int L = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) L += (int)S.fitc[w];
     const bool active = tid < L;   // fits is a prefix of the block
 
     if (tid == L - 1) {
@@ -422,8 +437,10 @@ fit_kernel(FitArgs a)
     }
 
     // block sums -> host-mapped partials (the host reduces them); the
-    // wavefront sums are uniform already
-    const int lane = tid & 63, wid = tid >> 6;
+    // wavefront sums are uniform already.  Lane and wave ids are recomputed
+    // here rather than kept live across the whole kernel.
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
     __shared__ BlockPartial s_part[kWaves];
     if (lane == 0)
         s_part[wid] = BlockPartial{acc.comb, acc.pass, acc.tracks, acc.err_road, acc.err_event, 0};
