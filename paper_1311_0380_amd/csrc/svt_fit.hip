@@ -215,29 +215,32 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         bad_hit_road = (uint32_t)(s + lo);
     }
     acc.err_road = min(acc.err_road, wave_min(bad_hit_road));
-    // bin starts: exclusive scan of the 289 bins by wave 0
-    if (tid < 64) {
+    // bin starts: every wavefront scans the 289 bins itself (lane l holds
+    // bins 5l .. 5l+4) and fetches its roads' starts across lanes, so no
+    // barrier separates the scan from the row lists
+    uint32_t bstart;
+    {
         uint32_t vb[5], loc = 0;
+        const int lb = (tid & 63) * 5;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const int b = tid * 5 + q;
-            vb[q] = b < kBins ? S.bin[b] : 0u;
+            vb[q] = lb + q < kBins ? S.bin[lb + q] : 0u;
             loc += vb[q];
         }
-        const uint32_t incl = wave_incl_scan(loc);
-        uint32_t run = incl - loc;
+        uint32_t run = wave_incl_scan(loc) - loc;
+        const int src = (int)(bkey / 5u), slot = (int)(bkey - (uint32_t)src * 5u);
+        bstart = 0;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const int b = tid * 5 + q;
-            if (b < kBins) S.bin[b] = run;
+            const uint32_t sq = (uint32_t)__shfl((int)run, src, 64);
+            bstart = slot == q ? sq : bstart;
             run += vb[q];
         }
     }
-    __syncthreads();
 
     // rows of the road, in (i0, i1) order, at its place in the binned list
     if (active && rows) {
-        uint32_t w = S.bin[bkey] + boff;
+        uint32_t w = bstart + boff;
         for (uint32_t i0 = 0; i0 < n0; ++i0)
             for (uint32_t i1 = 0; i1 < n1; ++i1, ++w)
                 S.row[w] = (uint16_t)(tid | (i0 << 8) | (i1 << 12));
