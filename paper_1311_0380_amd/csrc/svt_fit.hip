@@ -85,6 +85,7 @@ struct Shared {
     uint16_t row[kRowCap];                  // road | i0 << 8 | i1 << 12, binned by (n2, n3)
     int16_t hit[kHitCap + 16];              // staged hit words (+ pad read by row loops)
     uint32_t bin[kBins];
+    uint32_t bstart[kBins];
     int32_t evro[kMaxEventsPerChunk + 1];
     uint32_t evcnt[kMaxEventsPerChunk];
     uint64_t warp[kWaves];
@@ -228,22 +229,37 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
             loc += vb[q];
         }
         uint32_t run = wave_incl_scan(loc) - loc;
-        const int src = (int)(bkey / 5u), slot = (int)(bkey - (uint32_t)src * 5u);
-        bstart = 0;
+        // every wavefront writes the same starts, so a wavefront reading
+        // after its own writes sees the right value whoever wrote last
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const uint32_t sq = (uint32_t)__shfl((int)run, src, 64);
-            bstart = slot == q ? sq : bstart;
+            if (lb + q < kBins) S.bstart[lb + q] = run;
             run += vb[q];
         }
+        wave_sync();
+        bstart = S.bstart[bkey];
     }
 
     // rows of the road, in (i0, i1) order, at its place in the binned list
     if (active && rows) {
-        uint32_t w = bstart + boff;
-        for (uint32_t i0 = 0; i0 < n0; ++i0)
-            for (uint32_t i1 = 0; i1 < n1; ++i1, ++w)
-                S.row[w] = (uint16_t)(tid | (i0 << 8) | (i1 << 12));
+        // the road's rows in (i0, i1) order at [w, w + rows): an odd first
+        // slot alone, then two rows per 32-bit store
+        uint32_t w = bstart + boff, i0 = 0, i1 = 0, k = 0;
+        const uint32_t base = (uint32_t)tid;
+        if (w & 1u) {
+            S.row[w++] = (uint16_t)base;
+            k = 1;
+            i1 = 1 == n1 ? 0u : 1u;
+            i0 = 1 == n1 ? 1u : 0u;
+        }
+        for (; k + 1 < rows; k += 2, w += 2) {
+            const uint32_t ra = base | (i0 << 8) | (i1 << 12);
+            if (++i1 == n1) { i1 = 0; ++i0; }
+            const uint32_t rb2 = base | (i0 << 8) | (i1 << 12);
+            if (++i1 == n1) { i1 = 0; ++i0; }
+            *reinterpret_cast<uint32_t *>(&S.row[w]) = ra | (rb2 << 16);
+        }
+        if (k < rows) S.row[w] = (uint16_t)(base | (i0 << 8) | (i1 << 12));
     }
     __syncthreads();
     for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;   // ready for the next sub-chunk
