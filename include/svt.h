@@ -114,8 +114,11 @@ typedef struct {
     int32_t err_road;       /* lowest malformed road, -1 if none                  */
     int32_t err_event;      /* lowest malformed event, -1 if none                 */
     int32_t status;         /* status of the request (same as svt_result returns) */
-    int64_t device_ns;      /* device time between the request's first and last
-                               command (copies included)                          */
+    int64_t device_ns;      /* device time of the request: the fit kernel's own
+                               dispatch when the request is that kernel alone
+                               (device or mapped buffers, no comb_offsets);
+                               otherwise from the first to the last command,
+                               copies included                                     */
 } svt_summary;
 
 /* Launch shape of the fit.  Kernel 1 (the default) gives each block a chunk

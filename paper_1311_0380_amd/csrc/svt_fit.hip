@@ -20,6 +20,8 @@
 //
 // Each block writes its partial sums to host-mapped memory; the host reduces
 // them when the request completes.
+#include <hip/hip_ext.h>
+
 #include "svt_internal.h"
 #include "svt_rows.h"
 
@@ -549,9 +551,14 @@ hipError_t prepare_fit()
                                hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
 }
 
-hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream)
+hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream,
+                      hipEvent_t start, hipEvent_t stop)
 {
-    hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), dyn_lds, stream, a);
+    if (start != nullptr || stop != nullptr)
+        hipExtLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), (uint32_t)dyn_lds, stream, start,
+                              stop, 0u, a);
+    else
+        hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), dyn_lds, stream, a);
     return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@
 //      order is the order of (chi2, combination index) since every n_l <= 16.
 //   C  lane = road: decode the winner, recompute its parameter rows 0..2 in
 //      int32, write the road's results, count tracks per event.
+#include <hip/hip_ext.h>
+
 #include "svt_internal.h"
 #include "svt_rows.h"
 
@@ -408,10 +410,15 @@ hipError_t prepare_fit_wave()
                                hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
 }
 
-hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream)
+hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream, hipEvent_t start,
+                           hipEvent_t stop)
 {
     const size_t dyn = (size_t)a.n_sectors * kCstPbStride * sizeof(double);
-    hipLaunchKernelGGL(fit_wave_kernel, dim3(grid), dim3(kBlock), dyn, stream, a);
+    if (start != nullptr || stop != nullptr)
+        hipExtLaunchKernelGGL(fit_wave_kernel, dim3(grid), dim3(kBlock), (uint32_t)dyn, stream,
+                              start, stop, 0u, a);
+    else
+        hipLaunchKernelGGL(fit_wave_kernel, dim3(grid), dim3(kBlock), dyn, stream, a);
     return hipGetLastError();
 }
 

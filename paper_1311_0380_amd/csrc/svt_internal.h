@@ -96,9 +96,13 @@ struct FitArgs {
 };
 
 hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
-hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream);
+// start/stop non-NULL: the dispatch itself records them around the kernel
+// (no separate event packets on the stream).
+hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream,
+                      hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t prepare_fit_wave();
-hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream);
+hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream,
+                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
                                int64_t *scratch, hipStream_t stream);
 size_t comb_offsets_scratch_bytes(int32_t n_roads);

@@ -267,7 +267,7 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
 }
 
 hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &ls,
-                         hipStream_t st)
+                         hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr)
 {
     const char *w = static_cast<const char *>(c->cst_wave);
     a.cst_pb = reinterpret_cast<const double *>(w);
@@ -277,8 +277,9 @@ hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &l
     a.frac_key = c->cut < (1ull << 44) ? 1 : 0;
     a.cst_block = static_cast<const double *>(c->cst_block);
     a.events_per_chunk = ls.epc;
-    if (ls.kernel == 2) return svt::launch_fit_wave(a, ls.grid, st);
-    return svt::launch_fit(a, ls.grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st);
+    if (ls.kernel == 2) return svt::launch_fit_wave(a, ls.grid, st, start, stop);
+    return svt::launch_fit(a, ls.grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st, start,
+                           stop);
 }
 
 // Call-level validation shared by the fit entry points.
@@ -597,7 +598,11 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     a.offset = c->offset;
     a.cut_d = (double)c->cut;
 
-    HIP_TRY(hipEventRecord(s.ev_start, st));
+    // a request that is the kernel alone is timed by its dispatch (no event
+    // packets of its own on the stream); copies or the offsets scan need
+    // events around the whole request
+    const bool kernel_only = !stage_in && !stage_out && res->comb_offsets == nullptr;
+    if (!kernel_only) HIP_TRY(hipEventRecord(s.ev_start, st));
     if (stage_in) {
         const hipMemcpyKind k = hipMemcpyHostToDevice;
         HIP_TRY(hipMemcpyAsync(base + o_ro, b->road_offsets, b_ro, k, st));
@@ -654,7 +659,8 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     s.parts = s.partials;
     s.plan = nullptr;
 
-    hipError_t e = launch_shaped(c, a, ls, st);
+    hipError_t e = kernel_only ? launch_shaped(c, a, ls, st, s.ev_start, s.ev_end)
+                               : launch_shaped(c, a, ls, st);
     if (e != hipSuccess) return hip_fail(e, "fit kernel launch");
     if (co_dev) {
         e = svt::launch_comb_offsets(a.ncomb, co_dev, nr, static_cast<int64_t *>(s.scan.ptr), st);
@@ -673,7 +679,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         if (ne) HIP_TRY(hipMemcpyAsync(res->ntracks, a.ntracks, b_ntr, k, st));
         if (co_dev) HIP_TRY(hipMemcpyAsync(res->comb_offsets, co_dev, b_co, k, st));
     }
-    HIP_TRY(hipEventRecord(s.ev_end, st));
+    if (!kernel_only) HIP_TRY(hipEventRecord(s.ev_end, st));
     guard.keep = true;
     s.busy = true;
     s.ticket = c->next_ticket++;
