@@ -6,15 +6,18 @@
 // hits (kHitCap) and (i0, i1) rows (kRowCap) fit in LDS:
 //
 //   A  one thread per road: load + validate the road, prefix sums give each
-//      road its slot in the LDS hit table and row list; the road's rows are
-//      binned by (n2, n3) so that a wavefront's rows share their inner trip
-//      counts; the hits are staged in LDS as fp64 (coalesced, flattened);
-//      the constraint rows' constant part b + A[:,4] x4 + A[:,5] x5 is formed.
-//   B  one thread per row (i0, i1): z = base + A[:,0] h0 + A[:,1] h1, then
-//      every (i2, i3) combination in the row loops of svt_rows.h.  The row's
-//      best is merged into the road with one LDS atomicMin on the key
-//      chi2 << 16 | i0 << 12 | i1 << 8 | i2 << 4 | i3, whose order is the
-//      order of (chi2, combination index k) because each i_l < n_l <= 16.
+//      road its slot in the LDS hit table and row list.  The road's two
+//      layers with the fewest hits index its rows (c, d) and the other two
+//      (a, b) are looped over inside each row, which gives the fewest and
+//      longest rows.  Rows are binned by (n_a, n_b) so that a wavefront's
+//      rows share their inner trip counts; the hits are staged in LDS
+//      (coalesced, flattened); the constraint rows' constant part
+//      b + A[:,4] x4 + A[:,5] x5 is formed.
+//   B  one thread per row (i_c, i_d): z = base + A[:,c] h_c + A[:,d] h_d,
+//      then every (i_a, i_b) combination in the row loops of svt_rows.h.
+//      The row's best is merged into the road with one LDS atomicMin on the
+//      key chi2 << 16 | i0 << 12 | i1 << 8 | i2 << 4 | i3, whose order is
+//      the order of (chi2, combination index k) because each i_l < n_l <= 16.
 //   C  one thread per road: decode the winner, recompute its parameter rows
 //      0..2 exactly in int32, write the road's results, count tracks per event.
 //
@@ -30,6 +33,7 @@ namespace {
 
 constexpr int kBins = 17 * 17;   // (n2, n3) in 0..16 x 0..16
 constexpr int kWaves = kBlock / 64;
+static_assert(kMaxEventsPerChunk <= kBlock, "one thread per event of a chunk");
 
 // Inclusive scans across the wavefront: of two packed 32-bit counters
 // (neither half may overflow), and of one 64-bit value.
@@ -80,6 +84,10 @@ struct Acc {
 
 struct Shared {
     double base[3][kSubRoads];              // b + A[:,4] x4 + A[:,5] x5, rows 3..5
+    // per road: staged hit index of the first hit of layers a, b (x) and
+    // c, d (y); n_a | n_b << 8 | (a | b << 2 | c << 4 | d << 6) << 16 (z);
+    // sector (w)
+    uint4 rec[kSubRoads];
     unsigned long long key[kSubRoads];      // best key of each road
     uint32_t n4[kSubRoads];                 // packed hit counts of each road
     uint32_t np[kSubRoads];                 // passing combinations of each road
@@ -92,7 +100,6 @@ struct Shared {
     uint32_t evcnt[kMaxEventsPerChunk];
     uint64_t warp[kWaves];
     uint32_t fitc[kWaves];
-    uint8_t sec[kSubRoads];
     int32_t misc[4];
 };
 
@@ -142,7 +149,33 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
     acc.err_road = min(acc.err_road, wave_min(inr && !ok ? (uint32_t)r : 0xFFFFFFFFu));
 
     const uint32_t nh = ok ? sum : 0u;
-    const uint32_t rows = (ok && n2 * n3 > 0) ? n0 * n1 : 0u;
+    // row layers c < d: the two with the fewest hits (ties to the lower
+    // layer); inner layers a < b: the other two
+    uint32_t rowmask = 0;
+    {
+        const uint32_t nl[4] = {n0, n1, n2, n3};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            uint32_t rk = 0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (m != l) rk += (nl[m] < nl[l] || (nl[m] == nl[l] && m < l)) ? 1u : 0u;
+            rowmask |= (rk < 2 ? 1u : 0u) << l;
+        }
+    }
+    // the layers and their counts are derived again where they are used,
+    // which keeps only the mask live across the scan's barriers
+    auto lay = [](uint32_t m, int q) {   // q = 0..3: c, d, a, b
+        return q == 0 ? (uint32_t)__builtin_ctz(m)
+             : q == 1 ? 31u - (uint32_t)__builtin_clz(m)
+             : q == 2 ? (uint32_t)__builtin_ctz(m ^ 15u) : 31u - (uint32_t)__builtin_clz(m ^ 15u);
+    };
+    auto cnt = [](uint32_t c4, uint32_t l) { return (c4 >> (8 * l)) & 255u; };
+    auto off = [](uint32_t c4, uint32_t l) {   // hits of the layers before l
+        return ((c4 & ((1u << (8 * l)) - 1u)) * 0x01010101u) >> 24;
+    };
+    const uint32_t rows =
+        (ok && n0 * n1 * n2 * n3 > 0) ? cnt(nh4, lay(rowmask, 0)) * cnt(nh4, lay(rowmask, 1)) : 0u;
     // block scan of (hits, rows); the roads that fit are a prefix of the
     // block, counted per wave and summed across the scan's second barrier
     const uint64_t pk = (uint64_t)nh | ((uint64_t)rows << 32);
@@ -168,12 +201,20 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         S.misc[1] = (int32_t)(hb + nh);           // hits of the sub-chunk
         S.misc[3] = (int32_t)(rbase + rows);      // rows of the sub-chunk
     }
-    const uint32_t bkey = n3 * 17u + n2;   // n3 major: wavefronts share n3
+    const uint32_t bkey = cnt(nh4, lay(rowmask, 3)) * 17u + cnt(nh4, lay(rowmask, 2));   // n_b major
     uint32_t boff = 0;
     if (active) {
         S.hb[tid] = (uint16_t)hb;
+        {
+            const uint32_t lc = lay(rowmask, 0), ld = lay(rowmask, 1), la = lay(rowmask, 2),
+                           lb = lay(rowmask, 3);
+            S.rec[tid] = make_uint4((hb + off(nh4, la)) | ((hb + off(nh4, lb)) << 16),
+                                    (hb + off(nh4, lc)) | ((hb + off(nh4, ld)) << 16),
+                                    cnt(nh4, la) | (cnt(nh4, lb) << 8) |
+                                        ((la | (lb << 2) | (lc << 4) | (ld << 6)) << 16),
+                                    ok ? sec : 0u);
+        }
         S.n4[tid] = ok ? nh4 : 0u;
-        S.sec[tid] = (uint8_t)(ok ? sec : 0u);
         S.key[tid] = ~0ull;
         S.np[tid] = 0;
         if (rows) boff = atomicAdd(&S.bin[bkey], rows);
@@ -242,26 +283,26 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         bstart = S.bstart[bkey];
     }
 
-    // rows of the road, in (i0, i1) order, at its place in the binned list
+    // rows of the road, in (i_c, i_d) order, at its place in the binned list
     if (active && rows) {
-        // the road's rows in (i0, i1) order at [w, w + rows): an odd first
-        // slot alone, then two rows per 32-bit store
-        uint32_t w = bstart + boff, i0 = 0, i1 = 0, k = 0;
-        const uint32_t base = (uint32_t)tid;
+        // the road's rows at [w, w + rows): an odd first slot alone, then
+        // two rows per 32-bit store
+        uint32_t w = bstart + boff, ic = 0, id = 0, k = 0;
+        const uint32_t base = (uint32_t)tid, nd = cnt(nh4, lay(rowmask, 1));
         if (w & 1u) {
             S.row[w++] = (uint16_t)base;
             k = 1;
-            i1 = 1 == n1 ? 0u : 1u;
-            i0 = 1 == n1 ? 1u : 0u;
+            id = 1 == nd ? 0u : 1u;
+            ic = 1 == nd ? 1u : 0u;
         }
         for (; k + 1 < rows; k += 2, w += 2) {
-            const uint32_t ra = base | (i0 << 8) | (i1 << 12);
-            if (++i1 == n1) { i1 = 0; ++i0; }
-            const uint32_t rb2 = base | (i0 << 8) | (i1 << 12);
-            if (++i1 == n1) { i1 = 0; ++i0; }
+            const uint32_t ra = base | (ic << 8) | (id << 12);
+            if (++id == nd) { id = 0; ++ic; }
+            const uint32_t rb2 = base | (ic << 8) | (id << 12);
+            if (++id == nd) { id = 0; ++ic; }
             *reinterpret_cast<uint32_t *>(&S.row[w]) = ra | (rb2 << 16);
         }
-        if (k < rows) S.row[w] = (uint16_t)(base | (i0 << 8) | (i1 << 12));
+        if (k < rows) S.row[w] = (uint16_t)(base | (ic << 8) | (id << 12));
     }
     __syncthreads();
     for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;   // ready for the next sub-chunk
@@ -272,31 +313,40 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         const int idx = idx0 + tid;
         const bool act = idx < total_rows;
         const uint32_t d = S.row[act ? idx : total_rows - 1];
-        const uint32_t j = d & 255u, i0 = (d >> 8) & 15u, i1 = (d >> 12) & 15u;
-        const uint32_t rn = S.n4[j], hbj = S.hb[j];
-        const uint32_t rn0 = rn & 255u, rn1 = (rn >> 8) & 255u, rn2 = (rn >> 16) & 255u,
-                       rn3 = rn >> 24;
-        const uint32_t p2 = hbj + rn0 + rn1;
-        const double *cs = s_cd + (uint32_t)S.sec[j] * kCstStride;
-        const double h0v = (double)S.hit[hbj + i0], h1v = (double)S.hit[hbj + rn0 + i1];
+        const uint32_t j = d & 255u, ic = (d >> 8) & 15u, id = (d >> 12) & 15u;
+        const uint4 rc = S.rec[j];
+        const uint32_t rn2 = rc.z & 255u, rn3 = (rc.z >> 8) & 255u;
+        const uint32_t la = (rc.z >> 16) & 3u, lb = (rc.z >> 18) & 3u, lc = (rc.z >> 20) & 3u,
+                       ld = (rc.z >> 22) & 3u;
+        // sector constants: column l of rows 3..5 at cs[3 l .. 3 l + 2]
+        const double *cs = s_cd + rc.w * kCstStride;
+        const double *ka = cs + 3 * la, *kb = cs + 3 * lb, *kc = cs + 3 * lc, *kd = cs + 3 * ld;
+        const double hc = (double)S.hit[(rc.y & 0xFFFFu) + ic], hd = (double)S.hit[(rc.y >> 16) + id];
         Row st;
-        st.z3 = fma(cs[3], h1v, fma(cs[0], h0v, S.base[0][j]));
-        st.z4 = fma(cs[4], h1v, fma(cs[1], h0v, S.base[1][j]));
-        st.z5 = fma(cs[5], h1v, fma(cs[2], h0v, S.base[2][j]));
-        st.a3 = cs[6];
-        st.a4 = cs[7];
-        st.a5 = cs[8];
-        st.c3 = cs[9];
-        st.c4 = cs[10];
-        st.c5 = cs[11];
+        st.z3 = fma(kd[0], hd, fma(kc[0], hc, S.base[0][j]));
+        st.z4 = fma(kd[1], hd, fma(kc[1], hc, S.base[1][j]));
+        st.z5 = fma(kd[2], hd, fma(kc[2], hc, S.base[2][j]));
+        st.a3 = ka[0];
+        st.a4 = ka[1];
+        st.a5 = ka[2];
+        st.c3 = kb[0];
+        st.c4 = kb[1];
+        st.c5 = kb[2];
         st.best = F ? __builtin_inf() : cut + 1.0;
         st.bidx = 0xFFFFFFFFu;
         st.np = 0;
-        run_row<F>(st, S.hit, p2, rn2, rn3, F ? cut + 0.5 : cut);
+        run_row<F>(st, S.hit, rc.x & 0xFFFFu, rc.x >> 16, rn2, rn3, F ? cut + 0.5 : cut);
         if (act) {
+            // the row's indices and layers come back from LDS rather than
+            // staying live across the row loops
+            const uint32_t d2 = S.row[idx];
+            const uint32_t j2 = d2 & 255u, lay = S.rec[j2].z >> 16;
+            const uint32_t rowbits = (((d2 >> 8) & 15u) << (12u - 4u * ((lay >> 4) & 3u))) |
+                                     (((d2 >> 12) & 15u) << (12u - 4u * ((lay >> 6) & 3u)));
             unsigned long long key;
-            if (row_key<F>(st, cut, i0, i1, key)) atomicMin(&S.key[j], key);
-            if (st.np) atomicAdd(&S.np[j], st.np);
+            if (row_key<F>(st, cut, rowbits, 12u - 4u * (lay & 3u), 12u - 4u * ((lay >> 2) & 3u), key))
+                atomicMin(&S.key[j2], key);
+            if (st.np) atomicAdd(&S.np[j2], st.np);
         }
     }
     __syncthreads();
@@ -306,7 +356,7 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
     // the road's error path), which keeps phase A's values out of phase B.
     uint32_t my_comb = 0, my_pass = 0, my_track = 0;
     if (active) {
-        const uint32_t c4 = S.n4[tid], hb = S.hb[tid], sec = S.sec[tid];
+        const uint32_t c4 = S.n4[tid], hb = S.hb[tid], sec = S.rec[tid].w;
         const uint32_t n0 = c4 & 255u, n1 = (c4 >> 8) & 255u, n2 = (c4 >> 16) & 255u,
                        n3 = c4 >> 24;
         const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
@@ -438,7 +488,7 @@ fit_kernel(FitArgs a)
         const int32_t ne = min(E, n_events - e0);
         if (c != c_first)
             for (int i = tid; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
-        for (int i = tid; i < ne; i += kBlock) S.evcnt[i] = 0;
+        if (tid < ne) S.evcnt[tid] = 0;   // ne <= kMaxEventsPerChunk = kBlock
         __syncthreads();
         const int32_t ra = clampi(S.evro[0], 0, n_roads);
         const int32_t rb = clampi(S.evro[ne], ra, n_roads);

@@ -205,10 +205,10 @@ __device__ int wave_sub(const FitArgs &a, WaveLds &W, const double *s_pb, int32_
         st.best = F ? __builtin_inf() : cut + 1.0;
         st.bidx = 0xFFFFFFFFu;
         st.np = 0;
-        run_row<F>(st, W.hit, hbj + rn0 + rn1, rn2, rn3, lim);
+        run_row<F>(st, W.hit, hbj + rn0 + rn1, hbj + rn0 + rn1 + rn2, rn2, rn3, lim);
         if (act) {
             unsigned long long key;
-            if (row_key<F>(st, cut, i0, i1, key)) atomicMin(&W.key[j], key);
+            if (row_key<F>(st, cut, (i0 << 12) | (i1 << 8), 4u, 0u, key)) atomicMin(&W.key[j], key);
             if (st.np) atomicAdd(&W.np[j], st.np);
         }
     }

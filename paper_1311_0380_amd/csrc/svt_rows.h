@@ -1,6 +1,10 @@
 // Row loops of the SVT fit shared by the fit kernels (arXiv:1311.0380,
-// Sec. 2): for one (i0, i1) row of a road, every (i2, i3) combination's
-// constraint rows y3..y5 and chi2 in fp64, the pass count and the best.
+// Sec. 2).  A road's combinations are split into rows: two of its layers
+// index the rows, the other two (the inner layers, a before b in layer
+// order) are looped over inside each row.  For one row these loops give
+// every combination's constraint rows y3..y5 and chi2 in fp64, the pass
+// count and the best.  Below, p2/n2 are the staged hit list and hit count
+// of inner layer a, p3/n3 those of inner layer b.
 //
 // Every quantity is an integer below 2^53 whenever chi2 <= cut < 2^48, so
 // the cut, the count and the minimum are exact.  When cut < 2^44 the
@@ -10,7 +14,9 @@
 // lowest index.  Otherwise a compare-and-select keeps them (general form).
 //
 // Rows are expected sorted by (n3, n2) within a wavefront, so that the last
-// lane holds the wavefront's largest (n3, n2); every lane is active.
+// lane holds the wavefront's largest (n3, n2); every lane is active.  Within
+// a row the combinations run in (i_a, i_b) order, which is their order in
+// the combination index k because a comes before b.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -99,7 +105,7 @@ struct Row {
     double a3, a4, a5;   // column of layer 2
     double c3, c4, c5;   // column of layer 3
     double best;         // fraction form: chi2 + idx / 256; else chi2 of the best
-    uint32_t bidx;       // (i2 << 4) | i3 of the best (general form), ~0 if none
+    uint32_t bidx;       // (i_a << 4) | i_b of the best (general form), ~0 if none
     uint32_t np;         // passing combinations
 };
 
@@ -117,21 +123,26 @@ __device__ __forceinline__ double dmin(double a, double b)
 }
 
 // The road key of a row's best, chi2 << 16 | i0 << 12 | i1 << 8 | i2 << 4 | i3,
-// and whether the row has a passing combination.  In the fraction form
-// 256 * best = 256 chi2 + (i2 * 16 + i3) is an integer below 2^52, which
+// and whether the row has a passing combination.  rowbits holds the row
+// layers' indices at their places in the key; sa and sb are the places
+// (12 - 4 * layer) of inner layers a and b.  In the fraction form
+// 256 * best = 256 chi2 + (i_a * 16 + i_b) is an integer below 2^52, which
 // fma(best, 256, 2^52) places in the low mantissa bits exactly.
 template <bool F>
-__device__ __forceinline__ bool row_key(const Row &st, double cut, uint32_t i0, uint32_t i1,
-                                        unsigned long long &key)
+__device__ __forceinline__ bool row_key(const Row &st, double cut, uint32_t rowbits, uint32_t sa,
+                                        uint32_t sb, unsigned long long &key)
 {
     if constexpr (F) {
         const double t = fma(st.best, 256.0, 0x1p52);
         const unsigned long long k =
             (unsigned long long)__double_as_longlong(t) & 0x000FFFFFFFFFFFFFull;
-        key = ((k >> 8) << 16) | (i0 << 12) | (i1 << 8) | (k & 255u);
+        const uint32_t lo = (uint32_t)k;
+        key = ((k >> 8) << 16) |
+              (rowbits | (((lo >> 4) & 15u) << sa) | ((lo & 15u) << sb));
         return st.best < cut + 1.0;
     } else {
-        key = ((unsigned long long)st.best << 16) | (i0 << 12) | (i1 << 8) | st.bidx;
+        key = ((unsigned long long)st.best << 16) |
+              (rowbits | (((st.bidx >> 4) & 15u) << sa) | ((st.bidx & 15u) << sb));
         return st.bidx != 0xFFFFFFFFu;
     }
 }
@@ -143,10 +154,9 @@ __device__ __forceinline__ bool row_key(const Row &st, double cut, uint32_t i0, 
 // wavefronts only) is clamped into the list, computes a duplicate with a
 // larger fraction that never wins and is kept out of the pass count.
 template <int N2, int N3, bool UNI>
-__device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
-                                           uint32_t n3, double lim)
+__device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                           uint32_t n2, uint32_t n3, double lim)
 {
-    const uint32_t p3 = p2 + n2;
     const uint32_t l3 = n3 - 1;
     double h2[N2], h3[N3];
 #pragma unroll
@@ -178,11 +188,10 @@ __device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t
 }
 
 template <int N3>
-__device__ __forceinline__ void frac_uniform(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
-                                             uint32_t n2w, double lim)
+__device__ __forceinline__ void frac_uniform(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                             uint32_t n2, uint32_t n2w, double lim)
 {
     constexpr int H = N3 <= 8 ? N3 : 1;
-    const uint32_t p3 = p2 + n2;
     double h3[H];
     if constexpr (N3 <= 8) {
 #pragma unroll
@@ -229,10 +238,10 @@ __device__ __forceinline__ void frac_uniform(Row &st, const int16_t *hit, uint32
 // Rows of different (n2, n3) in one wavefront: indices are clamped into the
 // row's lists.  A clamped duplicate has the chi2 of a real combination and a
 // larger fraction, so it never wins; it is kept out of the pass count.
-__device__ __forceinline__ void frac_mixed(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
-                                           uint32_t n3, uint32_t n2w, uint32_t n3w, double lim)
+__device__ __forceinline__ void frac_mixed(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                           uint32_t n2, uint32_t n3, uint32_t n2w, uint32_t n3w,
+                                           double lim)
 {
-    const uint32_t p3 = p2 + n2;
     double f2 = 0.0;
     for (uint32_t i2 = 0; i2 < n2w; ++i2, f2 += 1.0 / 16) {
         const double h2 = (double)hit[p2 + (i2 < n2 ? i2 : n2 - 1)];
@@ -269,10 +278,9 @@ __device__ __forceinline__ void gen_combo(Row &st, double q3, double q4, double 
 }
 
 template <int N3>
-__device__ __forceinline__ void gen_uniform(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
-                                            uint32_t n2w, double cut)
+__device__ __forceinline__ void gen_uniform(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                            uint32_t n2, uint32_t n2w, double cut)
 {
-    const uint32_t p3 = p2 + n2;
     for (uint32_t i2 = 0; i2 < n2w; ++i2) {
         if (i2 < n2) {
             const double h2 = (double)hit[p2 + i2];
@@ -286,10 +294,10 @@ __device__ __forceinline__ void gen_uniform(Row &st, const int16_t *hit, uint32_
     }
 }
 
-__device__ __forceinline__ void gen_mixed(Row &st, const int16_t *hit, uint32_t p2, uint32_t n2,
-                                          uint32_t n3, uint32_t n2w, uint32_t n3w, double cut)
+__device__ __forceinline__ void gen_mixed(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                          uint32_t n2, uint32_t n3, uint32_t n2w, uint32_t n3w,
+                                          double cut)
 {
-    const uint32_t p3 = p2 + n2;
     const double never = cut + 2.0;
     for (uint32_t i2 = 0; i2 < n2w; ++i2) {
         const double h2 = (double)hit[p2 + (i2 < n2 ? i2 : n2 - 1)];
@@ -312,8 +320,8 @@ __device__ __forceinline__ void gen_mixed(Row &st, const int16_t *hit, uint32_t 
 }
 
 template <bool F>
-__device__ __forceinline__ void run_row(Row &st, const int16_t *hit, uint32_t p2, uint32_t rn2,
-                                        uint32_t rn3, double lim)
+__device__ __forceinline__ void run_row(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                        uint32_t rn2, uint32_t rn3, double lim)
 {
     // rows are sorted by (n3, n2): the last lane holds the wavefront's largest
     const uint32_t n3f = __builtin_amdgcn_readfirstlane(rn3);
@@ -327,8 +335,8 @@ __device__ __forceinline__ void run_row(Row &st, const int16_t *hit, uint32_t p2
             const uint32_t sel = ((n2m - 1) << 2) | (n3w - 1);
 #define SVT_SMALL(N2, N3)                                                             \
     case ((N2 - 1) << 2) | (N3 - 1):                                                  \
-        if (n3f == n3l) frac_small<N2, N3, true>(st, hit, p2, rn2, rn3, lim);         \
-        else frac_small<N2, N3, false>(st, hit, p2, rn2, rn3, lim);                   \
+        if (n3f == n3l) frac_small<N2, N3, true>(st, hit, p2, p3, rn2, rn3, lim);     \
+        else frac_small<N2, N3, false>(st, hit, p2, p3, rn2, rn3, lim);               \
         return;
             switch (sel) {
                 SVT_SMALL(1, 1) SVT_SMALL(1, 2) SVT_SMALL(1, 3) SVT_SMALL(1, 4)
@@ -343,8 +351,8 @@ __device__ __forceinline__ void run_row(Row &st, const int16_t *hit, uint32_t p2
     if (n3f == n3l) {
 #define SVT_CASE(N)                                                          \
     case N:                                                                  \
-        if constexpr (F) frac_uniform<N>(st, hit, p2, rn2, n2w, lim);        \
-        else gen_uniform<N>(st, hit, p2, rn2, n2w, lim);                     \
+        if constexpr (F) frac_uniform<N>(st, hit, p2, p3, rn2, n2w, lim);    \
+        else gen_uniform<N>(st, hit, p2, p3, rn2, n2w, lim);                 \
         break;
         switch (n3f) {
             SVT_CASE(1) SVT_CASE(2) SVT_CASE(3) SVT_CASE(4) SVT_CASE(5) SVT_CASE(6)
@@ -355,8 +363,8 @@ __device__ __forceinline__ void run_row(Row &st, const int16_t *hit, uint32_t p2
 #undef SVT_CASE
     } else {
         const uint32_t n2m = wave_max(rn2);
-        if constexpr (F) frac_mixed(st, hit, p2, rn2, rn3, n2m, n3l, lim);
-        else gen_mixed(st, hit, p2, rn2, rn3, n2m, n3l, lim);
+        if constexpr (F) frac_mixed(st, hit, p2, p3, rn2, rn3, n2m, n3l, lim);
+        else gen_mixed(st, hit, p2, p3, rn2, rn3, n2m, n3l, lim);
     }
 }
 
