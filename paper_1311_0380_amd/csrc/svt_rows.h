@@ -122,6 +122,16 @@ __device__ __forceinline__ double dmin(double a, double b)
     return r;
 }
 
+// np += (v <= lim) as one compare into VCC and one add of its carry, in
+// place of a compare, a select and an add.
+__device__ __forceinline__ void count_le(uint32_t &np, double v, double lim)
+{
+    asm("v_cmp_le_f64_e32 vcc, %1, %2\n\tv_addc_co_u32_e32 %0, vcc, 0, %0, vcc"
+        : "+v"(np)
+        : "v"(v), "v"(lim)
+        : "vcc");
+}
+
 // The road key of a row's best, chi2 << 16 | i0 << 12 | i1 << 8 | i2 << 4 | i3,
 // and whether the row has a passing combination.  rowbits holds the row
 // layers' indices at their places in the key; sa and sb are the places
@@ -176,8 +186,12 @@ __device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t
                 const double y5 = fma(st.c5, h3[i3], q5);
                 const double v =
                     fma(y5, y5, fma(y4, y4, fma(y3, y3, (i2 * 16 + i3) * (1.0 / 256))));
-                const bool pass = v <= lim && (UNI || (uint32_t)i3 < n3);
-                st.np += pass ? 1u : 0u;
+                if constexpr (UNI) {
+                    count_le(st.np, v, lim);
+                } else {
+                    const bool pass = v <= lim && (uint32_t)i3 < n3;
+                    st.np += pass ? 1u : 0u;
+                }
                 st.best = dmin(st.best, v);
             }
         }
@@ -214,7 +228,7 @@ __device__ __forceinline__ void frac_uniform(Row &st, const int16_t *hit, uint32
                     const double y4 = fma(st.c4, h3[i3], q4);
                     const double y5 = fma(st.c5, h3[i3], q5);
                     const double v = fma(y5, y5, fma(y4, y4, fma(y3, y3, i3 * (1.0 / 256))));
-                    st.np += v <= lim ? 1u : 0u;
+                    count_le(st.np, v, lim);
                     bi = dmin(bi, v);
                 }
             } else {
@@ -226,7 +240,7 @@ __device__ __forceinline__ void frac_uniform(Row &st, const int16_t *hit, uint32
                     const double y4 = fma(st.c4, h, q4);
                     const double y5 = fma(st.c5, h, q5);
                     const double v = fma(y5, y5, fma(y4, y4, fma(y3, y3, f3)));
-                    st.np += v <= lim ? 1u : 0u;
+                    count_le(st.np, v, lim);
                     bi = dmin(bi, v);
                 }
             }
