@@ -95,8 +95,11 @@ struct svt_plan {
     size_t buf_bytes = 0;
     svt_event_batch in{};                   // device views of the input buffers
     svt_results out{};                      // device views of the result buffers
-    svt::Sizes *sizes_dev = nullptr;        // read by the captured kernel
-    svt::Sizes *sizes_host = nullptr;       // pinned; copied by the captured graph
+    // the batch's sizes: host-mapped, written by svt_plan_fit and read by the
+    // captured kernel through sizes_dev (its device view), so the graph needs
+    // no copy node
+    svt::Sizes *sizes_host = nullptr;
+    const svt::Sizes *sizes_dev = nullptr;
     svt::BlockPartial *partials = nullptr;  // host-mapped [grid]
     int grid = 0;
     svt_tuning tuning{};
@@ -896,7 +899,6 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
     const size_t o_par = off; off = align_up(off + 12 * nr, 256);
     const size_t o_hi = off; off = align_up(off + 4 * nr, 256);
     const size_t o_ntr = off; off = align_up(off + 4 * ne, 256);
-    const size_t o_sz = off; off = align_up(off + sizeof(svt::Sizes), 256);
     svt_status st = dev_alloc(c, &p->buf, off);
     if (st != SVT_OK) {
         delete p;
@@ -918,10 +920,9 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
                          reinterpret_cast<int32_t *>(base + o_par),
                          reinterpret_cast<uint8_t *>(base + o_hi),
                          reinterpret_cast<int32_t *>(base + o_ntr), nullptr, SVT_MEM_DEVICE, 0};
-    p->sizes_dev = reinterpret_cast<svt::Sizes *>(base + o_sz);
     p->grid = ls.grid;
     if (hipHostMalloc(reinterpret_cast<void **>(&p->sizes_host), sizeof(svt::Sizes),
-                      hipHostMallocDefault) != hipSuccess ||
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&p->partials),
                       sizeof(svt::BlockPartial) * p->grid,
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
@@ -930,6 +931,7 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
         return st;
     }
     memset(p->sizes_host, 0, sizeof(svt::Sizes));
+    p->sizes_dev = static_cast<const svt::Sizes *>(device_view(p->sizes_host, SVT_MEM_MAPPED));
     memset(p->partials, 0, sizeof(svt::BlockPartial) * p->grid);
 
     svt::FitArgs a;
@@ -959,11 +961,8 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = hipMemcpyAsync(p->sizes_dev, p->sizes_host, sizeof(svt::Sizes),
-                                       hipMemcpyHostToDevice, cs);
         hipError_t e2 = launch_shaped(c, a, ls, cs);
         e = hipStreamEndCapture(cs, &p->graph);
-        if (e == hipSuccess && e1 != hipSuccess) e = e1;
         if (e == hipSuccess && e2 != hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
