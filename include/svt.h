@@ -130,7 +130,10 @@ typedef struct {
     int32_t blocks_per_cu;     /* grid = CUs * blocks_per_cu (1..16), fewer when
                                   there are fewer chunks; 0 = automatic           */
     int32_t schedule;          /* 1 = cyclic (item w -> worker w mod workers),
-                                  2 = blocked; 0 keeps the current value          */
+                                  2 = blocked, 3 = balanced by roads (kernel 1:
+                                  each block takes the events whose first road
+                                  falls in its equal share of the roads; kernel
+                                  2 treats 3 as 1); 0 keeps the current value    */
     int32_t kernel;            /* 0 = automatic (1), 1 = block per chunk,
                                   2 = wavefront per chunk                         */
 } svt_tuning;

@@ -418,8 +418,35 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
     return L;
 }
 
+// The first event e in [0, n_events] with road_offsets[e] >= t, found by one
+// wavefront: each round probes 64 evenly spaced events of the interval left
+// and keeps the gap where the comparison turns (three rounds for 10^4
+// events).  Every lane returns the same value.  For offsets that are not
+// nondecreasing the result is still some event in [0, n_events].
+__device__ __forceinline__ int32_t first_event_at(const int32_t *road_offsets, int32_t n_events, int64_t t)
+{
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    int32_t lo = -1, hi = n_events;   // the answer lies in (lo, hi]
+    while (hi - lo > 1) {
+        const int32_t step = (hi - lo - 1 + 63) / 64;
+        const int32_t p = lo + (lane + 1) * step;
+        const bool ge = p >= hi || (int64_t)road_offsets[p] >= t;
+        const uint64_t m = __ballot(ge);
+        if (m == 0) {
+            lo = __builtin_amdgcn_readlane(p, 63);
+        } else {
+            const int j = __ffsll((unsigned long long)m) - 1;
+            const int32_t pj = __builtin_amdgcn_readlane(p, j);
+            lo = j > 0 ? __builtin_amdgcn_readlane(p, j - 1) : lo;
+            hi = pj < hi ? pj : hi;
+        }
+    }
+    return hi;
+}
+
 // Static schedules (no shared counter): 1 = cyclic (chunk c -> block c mod
-// grid), 2 = blocked (block b owns a contiguous range of chunks).
+// grid), 2 = blocked (block b owns a contiguous range of chunks); schedule 3
+// (balanced by roads) is set up in the kernel.
 __device__ __forceinline__ void chunk_range(int32_t n_chunks, int32_t schedule, int32_t &first,
                                             int32_t &step, int32_t &last)
 {
@@ -456,36 +483,75 @@ fit_kernel(FitArgs a)
     Acc acc;
     const double cut = a.cut_d;
     const int32_t E = a.events_per_chunk;
-    const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
+    // sector constants -> LDS: a copy of the image built at load time
+    const uint4 *csrc = reinterpret_cast<const uint4 *>(a.cst_block);
+    uint4 *cdst = reinterpret_cast<uint4 *>(s_cd);
+    const int n16 = n_sectors * kCstBytesPerSector / 16;
+
     int32_t c_first, c_step, c_last;
-    chunk_range(n_chunks, a.schedule, c_first, c_step, c_last);
+    // chunk c covers events [e_base + c E, min(e_base + (c + 1) E, e_end))
+    int32_t e_base = 0, e_end = n_events;
+    if (a.schedule == 3) {
+        // balanced by roads: block b takes the events whose first road lies
+        // in [b R / G, (b + 1) R / G) (R roads, G blocks), found by wavefronts
+        // 0 and 1; chunks of at most E events then split that range
+        // meanwhile wavefronts 2 and 3 stage the sector constants and check
+        // a share of the event offsets: every event's offsets are checked by
+        // some block whatever the partition, so that malformed offsets cannot
+        // escape the check
+        const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
+        const int64_t G = gridDim.x, b = blockIdx.x;
+        uint32_t bad_event = 0xFFFFFFFFu;
+        if (wid < 2) {
+            const int64_t bb = b + wid;
+            const int32_t e = bb >= G ? n_events
+                                      : first_event_at(a.road_offsets, n_events, (int64_t)n_roads * bb / G);
+            if (tid == wid * 64) S.misc[wid] = e;
+        } else {
+            const int t2 = tid - 128;
+            const int32_t per = (int32_t)((n_events + G - 1) / G);
+            for (int32_t e = (int32_t)(b * per) + t2; e < min((int64_t)n_events, (b + 1) * per); e += 128) {
+                const int32_t lo = a.road_offsets[e], hi = a.road_offsets[e + 1];
+                const bool bad = lo < 0 || hi < lo || hi > n_roads || (e == 0 && lo != 0) ||
+                                 (e == n_events - 1 && hi != n_roads);
+                if (bad) bad_event = min(bad_event, (uint32_t)e);
+            }
+            for (int i = t2; i < n16; i += 128) cdst[i] = csrc[i];
+        }
+        acc.err_event = min(acc.err_event, wave_min(bad_event));
+        __syncthreads();
+        e_base = clampi(S.misc[0], 0, n_events);
+        e_end = clampi(S.misc[1], e_base, n_events);
+        c_first = 0;
+        c_step = 1;
+        c_last = (e_end - e_base + E - 1) / E;
+        __syncthreads();   // S.misc is reused by the sub-chunks
+    } else {
+        const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
+        chunk_range(n_chunks, a.schedule, c_first, c_step, c_last);
+    }
 
     // the first chunk's event boundaries are in flight while the sector
     // constants are staged
     int32_t ev0 = 0, ev1 = 0;
     if (c_first < c_last) {
-        const int32_t e0 = c_first * E, ne = min(E, n_events - e0);
+        const int32_t e0 = e_base + c_first * E, ne = min(E, e_end - e0);
         if (tid <= ne) ev0 = a.road_offsets[e0 + tid];
         if (tid + kBlock <= ne) ev1 = a.road_offsets[e0 + tid + kBlock];
     }
 
-    // sector constants -> LDS: a copy of the image built at load time
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.cst_block);
-        uint4 *dst = reinterpret_cast<uint4 *>(s_cd);
-        const int n16 = n_sectors * kCstBytesPerSector / 16;
-        for (int i = tid; i < n16; i += kBlock) dst[i] = src[i];
-    }
+    if (a.schedule != 3)
+        for (int i = tid; i < n16; i += kBlock) cdst[i] = csrc[i];
     for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;
 
     if (c_first < c_last) {
-        const int32_t ne = min(E, n_events - c_first * E);
+        const int32_t ne = min(E, e_end - (e_base + c_first * E));
         if (tid <= ne) S.evro[tid] = ev0;
         if (tid + kBlock <= ne) S.evro[tid + kBlock] = ev1;
     }
     for (int32_t c = c_first; c < c_last; c += c_step) {
-        const int32_t e0 = c * E;
-        const int32_t ne = min(E, n_events - e0);
+        const int32_t e0 = e_base + c * E;
+        const int32_t ne = min(E, e_end - e0);
         if (c != c_first)
             for (int i = tid; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
         if (tid < ne) S.evcnt[tid] = 0;   // ne <= kMaxEventsPerChunk = kBlock

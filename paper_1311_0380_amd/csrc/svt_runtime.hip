@@ -259,7 +259,11 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
         per_block = 1;
     }
     int64_t grid = (int64_t)c->cu_count * bpc;
-    if (!persistent) {
+    if (!persistent && ls.kernel == 1 && t.schedule == 3) {
+        // balanced by roads: at least 64 roads per block
+        const int64_t need = ((int64_t)nr + 63) / 64;
+        if (grid > need) grid = need;
+    } else if (!persistent) {
         const int64_t n_chunks = ne > 0 ? ((int64_t)ne + ls.epc - 1) / ls.epc : 0;
         const int64_t need = (n_chunks + per_block - 1) / per_block;
         if (grid > need) grid = need;
@@ -495,7 +499,7 @@ svt_status svt_set_tuning(svt_ctx *c, const svt_tuning *t)
     if (c == nullptr || t == nullptr) return SVT_E_INVAL;
     if (t->events_per_chunk < 0 || t->events_per_chunk > svt::kMaxEventsPerChunk) return SVT_E_INVAL;
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > svt::kMaxBlocksPerCu) return SVT_E_INVAL;
-    if (t->schedule < 0 || t->schedule > 2) return SVT_E_INVAL;
+    if (t->schedule < 0 || t->schedule > 3) return SVT_E_INVAL;
     if (t->kernel < 0 || t->kernel > 2) return SVT_E_INVAL;
     c->tuning.events_per_chunk = t->events_per_chunk;   // 0 = automatic
     c->tuning.blocks_per_cu = t->blocks_per_cu;         // 0 = automatic
@@ -870,7 +874,7 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
     if (tuning) {
         if (tuning->events_per_chunk < 0 || tuning->events_per_chunk > svt::kMaxEventsPerChunk ||
             tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > svt::kMaxBlocksPerCu ||
-            tuning->schedule < 0 || tuning->schedule > 2 || tuning->kernel < 0 ||
+            tuning->schedule < 0 || tuning->schedule > 3 || tuning->kernel < 0 ||
             tuning->kernel > 2) {
             delete p;
             return SVT_E_INVAL;

@@ -160,7 +160,11 @@ def restore_tuning(ctx):
     dict(kernel=1), dict(kernel=1, events_per_chunk=1), dict(kernel=1, events_per_chunk=7),
     dict(kernel=1, events_per_chunk=256), dict(kernel=1, blocks_per_cu=1, schedule=1),
     dict(kernel=1, blocks_per_cu=3, schedule=1), dict(kernel=1, blocks_per_cu=8, schedule=2),
-    dict(kernel=1, events_per_chunk=3, schedule=2)])
+    dict(kernel=1, events_per_chunk=3, schedule=2),
+    # balanced by roads: each block's event range split into chunks of E
+    dict(kernel=1, schedule=3), dict(kernel=1, schedule=3, events_per_chunk=1),
+    dict(kernel=1, schedule=3, events_per_chunk=5, blocks_per_cu=1),
+    dict(kernel=1, schedule=3, blocks_per_cu=16), dict(kernel=2, schedule=3)])
 def test_launch_shapes_same_bits(ctx, oracle_lib, tuning):
     from paper_1311_0380_amd import svt
     batch, consts = synth.cfg3(n_events=2000)
@@ -243,20 +247,30 @@ def test_range_errors_match_oracle(ctx, oracle_lib, name):
     assert summ["err_event"] == wsum["err_event"] == -1
 
 
-def test_event_offset_errors(ctx, oracle_lib):
+@pytest.mark.parametrize("schedule", [1, 3])
+def test_event_offset_errors(ctx, oracle_lib, schedule):
+    """Malformed event offsets give the oracle's status and lowest bad
+    event, also when the schedule partitions events by searching them."""
     from paper_1311_0380_amd import svt
     batch, consts = synth.cfg2(n_events=40)
     load(ctx, consts)
-    for mutate in (lambda b: b.road_offsets.__setitem__(5, b.road_offsets[6] + 3),
-                   lambda b: b.road_offsets.__setitem__(-1, b.road_offsets[-1] - 2),
-                   lambda b: b.road_offsets.__setitem__(0, 1)):
-        bad = _copy(batch)
-        mutate(bad)
-        rc, _, wsum = oracle_lib.fit_batch(bad, consts)
-        assert rc == svt.SVT_E_RANGE
-        st, summ, _ = lib_fit(ctx, bad)
-        assert st == svt.SVT_E_RANGE
-        assert summ["err_event"] == wsum["err_event"]
+    mutations = (lambda b: b.road_offsets.__setitem__(5, b.road_offsets[6] + 3),
+                 lambda b: b.road_offsets.__setitem__(-1, b.road_offsets[-1] - 2),
+                 lambda b: b.road_offsets.__setitem__(0, 1),
+                 lambda b: b.road_offsets.__setitem__(20, b.road_offsets[3]),
+                 lambda b: b.road_offsets.__setitem__(30, 10 ** 6))
+    try:
+        svt.check(svt.svt_set_tuning(ctx, kernel=1, schedule=schedule, blocks_per_cu=4))
+        for mutate in mutations:
+            bad = _copy(batch)
+            mutate(bad)
+            rc, _, wsum = oracle_lib.fit_batch(bad, consts)
+            assert rc == svt.SVT_E_RANGE
+            st, summ, _ = lib_fit(ctx, bad)
+            assert st == svt.SVT_E_RANGE
+            assert summ["err_event"] == wsum["err_event"]
+    finally:
+        restore_tuning(ctx)
 
 
 def test_invalid_calls(ctx):

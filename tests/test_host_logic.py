@@ -25,7 +25,9 @@ def test_candidates_are_valid_shapes(ne, nr):
         if c["kernel"] == 2:
             assert c["events_per_chunk"] <= 63
         assert 0 <= c["blocks_per_cu"] <= 16
-        assert c["schedule"] in (1, 2)
+        assert c["schedule"] in (1, 2, 3)
+        if c["schedule"] == 3:
+            assert c["kernel"] == 1
 
 
 def test_candidates_cover_both_kernels_on_the_uneven_workload():
