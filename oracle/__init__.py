@@ -6,8 +6,9 @@ it, and it imports nothing from the product path: inputs come in as plain
 numpy arrays.
 
 `fit()` wraps the plain-C nested loops in svt_oracle.c (paper Sec. 2 fit
-equation, Sec. 2.1 three nested loops).  The float-shadow functions live in
-`oracle.shadow`.
+equation, Sec. 2.1 three nested loops); `list_passing()` keeps every passing
+combination rather than the best per road.  The float-shadow functions live
+in `oracle.shadow`.
 """
 from __future__ import annotations
 
@@ -57,6 +58,11 @@ def lib():
         L.orc_check_constants.restype = ctypes.c_int
         L.orc_check_constants.argtypes = [ctypes.c_int32, P, P, ctypes.c_uint64]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_list_passing.restype = ctypes.c_int
+        L.orc_list_passing.argtypes = [ctypes.c_int32] * 3 + [P] * 6 + [ctypes.c_int32, P, P,
+                                                                       ctypes.c_uint64,
+                                                                       ctypes.c_int64] + \
+            [P] * 4 + [ctypes.POINTER(Summary)]
         _lib = L
     return _lib
 
@@ -108,6 +114,50 @@ def fit_batch(batch, consts, **kw):
     """Convenience wrapper taking objects with the batch / constants fields."""
     return fit(batch.road_offsets, batch.sector, batch.nhits, batch.hit_offsets, batch.hits,
                batch.xft, consts.coef, consts.offset, consts.chi2_cut, **kw)
+
+
+def list_passing(road_offsets, sector, nhits, hit_offsets, hits, xft, coef, offset, chi2_cut,
+                 capacity=None):
+    """Every passing combination, road by road in combination-index order.
+    Returns (status, dict(offsets, k, chi2, params), summary dict); with
+    capacity None the list is sized by a first counting run."""
+    ro = np.ascontiguousarray(road_offsets, np.int32)
+    sector = np.ascontiguousarray(sector, np.uint8)
+    nhits = np.ascontiguousarray(nhits, np.uint8).reshape(-1)
+    ho = np.ascontiguousarray(hit_offsets, np.int32)
+    hits = np.ascontiguousarray(hits, np.int16)
+    xft = np.ascontiguousarray(xft, np.int16).reshape(-1)
+    coef = np.ascontiguousarray(coef, np.int32)
+    offset = np.ascontiguousarray(offset, np.int32)
+    n_events, nr, nh = ro.shape[0] - 1, sector.shape[0], hits.shape[0]
+
+    def run(cap):
+        out = dict(offsets=np.zeros(nr + 1, np.int64), k=np.zeros(max(cap, 1), np.int32),
+                   chi2=np.zeros(max(cap, 1), np.uint64), params=np.zeros((max(cap, 1), 3), np.int32))
+        s = Summary()
+        rc = lib().orc_list_passing(n_events, nr, nh, _ptr(ro), _ptr(sector), _ptr(nhits), _ptr(ho),
+                                    _ptr(hits), _ptr(xft), int(coef.shape[0]), _ptr(coef),
+                                    _ptr(offset), ctypes.c_uint64(int(chi2_cut)),
+                                    ctypes.c_int64(int(cap)), _ptr(out["offsets"]), _ptr(out["k"]),
+                                    _ptr(out["chi2"]), _ptr(out["params"]), ctypes.byref(s))
+        n = min(int(out["offsets"][-1]), cap)
+        for f in ("k", "chi2", "params"):
+            out[f] = out[f][:n]
+        summ = dict(total_comb=s.total_comb, total_pass=s.total_pass, err_road=s.err_road,
+                    err_event=s.err_event)
+        return rc, out, summ
+
+    if capacity is None:
+        rc, out, summ = run(0)
+        if rc not in (OK, E_RANGE) or summ["err_road"] >= 0 or summ["err_event"] >= 0:
+            return rc, out, summ
+        capacity = summ["total_pass"]
+    return run(int(capacity))
+
+
+def list_passing_batch(batch, consts, **kw):
+    return list_passing(batch.road_offsets, batch.sector, batch.nhits, batch.hit_offsets,
+                        batch.hits, batch.xft, consts.coef, consts.offset, consts.chi2_cut, **kw)
 
 
 def max_threads() -> int:

@@ -15,7 +15,8 @@
  *   - chi2 = y3^2 + y4^2 + y5^2 with integer additions and multiplications
  *     only (Sec. 2);
  *   - the chi2 cut (chi2 <= cut passes) and the best passing combination per
- *     road: smallest chi2, ties to the lowest combination index.
+ *     road: smallest chi2, ties to the lowest combination index;
+ *   - optionally the list of every passing combination (orc_list_passing).
  * Readings where the paper is silent: the fit input is one combination
  * x = (h0[i0], h1[i1], h2[i2], h3[i3], xft0, xft1); combinations are counted
  * lexicographically with layer 0 most significant; no shift or rounding is
@@ -247,6 +248,102 @@ int orc_fit(int32_t n_events, int32_t n_roads, int32_t n_hits,
     summary->total_pass = tot_pass;
     summary->total_tracks = (int32_t)tot_trk;
     return ORC_OK;
+}
+
+/*
+ * Every passing combination (chi2 <= cut) of every road, road by road and in
+ * combination-index order within a road: the fit of Sec. 2 runs on all
+ * combinations, and this keeps each one that passes instead of only the
+ * best.  Plain nested loops as in fit_road.  offsets[n_roads + 1] receives
+ * the exclusive running count of passing combinations per road; entries
+ * [offsets[r], offsets[r + 1]) hold road r's combination index k, chi2 and
+ * fit rows 0..2.  The arrays must hold `capacity` entries; returns ORC_OK,
+ * ORC_E_INVAL, or ORC_E_RANGE for malformed data (as orc_fit) or when the
+ * list does not fit (offsets are then complete, entries past capacity are
+ * not written).
+ */
+int orc_list_passing(int32_t n_events, int32_t n_roads, int32_t n_hits,
+                     const int32_t *road_offsets, const uint8_t *sector, const uint8_t *nhits,
+                     const int32_t *hit_offsets, const int16_t *hits, const int16_t *xft,
+                     int32_t n_sectors, const int32_t *coef, const int32_t *offset, uint64_t cut,
+                     int64_t capacity, int64_t *offsets, int32_t *list_k, uint64_t *list_chi2,
+                     int32_t *list_params, orc_summary *summary)
+{
+    if (summary == NULL || road_offsets == NULL || offsets == NULL || capacity < 0)
+        return ORC_E_INVAL;
+    memset(summary, 0, sizeof *summary);
+    summary->err_road = -1;
+    summary->err_event = -1;
+    if (n_events < 0 || n_roads < 0 || n_hits < 0)
+        return ORC_E_INVAL;
+    if (n_roads > 0 && (sector == NULL || nhits == NULL || hit_offsets == NULL || xft == NULL))
+        return ORC_E_INVAL;
+    if (capacity > 0 && (list_k == NULL || list_chi2 == NULL || list_params == NULL))
+        return ORC_E_INVAL;
+    int rc = orc_check_constants(n_sectors, coef, offset, cut);
+    if (rc != ORC_OK)
+        return rc;
+    for (int32_t e = 0; e < n_events; ++e)
+        if (bad_event(e, n_events, n_roads, road_offsets)) {
+            summary->err_event = e;
+            break;
+        }
+    for (int32_t r = 0; r < n_roads; ++r)
+        if (bad_road(r, n_roads, n_hits, n_sectors, sector, nhits, hit_offsets, hits, xft)) {
+            summary->err_road = r;
+            break;
+        }
+    if (summary->err_event >= 0 || summary->err_road >= 0)
+        return ORC_E_RANGE;
+
+    int64_t at = 0;   /* entries so far, in road order */
+    for (int32_t r = 0; r < n_roads; ++r) {
+        offsets[r] = at;
+        const int s = sector[r];
+        const int n0 = nhits[r * 4 + 0], n1 = nhits[r * 4 + 1];
+        const int n2 = nhits[r * 4 + 2], n3 = nhits[r * 4 + 3];
+        const int16_t *h0 = hits + hit_offsets[r];
+        const int16_t *h1 = h0 + n0;
+        const int16_t *h2 = h1 + n1;
+        const int16_t *h3 = h2 + n2;
+        const int32_t *A = coef + s * 36;
+        const int32_t *b = offset + s * 6;
+        int32_t k = 0;
+        for (int i0 = 0; i0 < n0; ++i0)
+            for (int i1 = 0; i1 < n1; ++i1)
+                for (int i2 = 0; i2 < n2; ++i2)
+                    for (int i3 = 0; i3 < n3; ++i3, ++k) {
+                        const int64_t x[6] = {h0[i0], h1[i1], h2[i2], h3[i3],
+                                              xft[r * 2 + 0], xft[r * 2 + 1]};
+                        int64_t y[6];
+                        for (int row = 0; row < 6; ++row) {
+                            int64_t acc = b[row];
+                            for (int j = 0; j < 6; ++j)
+                                acc += (int64_t)A[row * 6 + j] * x[j];
+                            if (acc < INT32_MIN || acc > INT32_MAX) {
+                                fprintf(stderr, "oracle: fit row outside int32\n");
+                                abort();
+                            }
+                            y[row] = acc;
+                        }
+                        const uint64_t c2 = (uint64_t)(y[3] * y[3]) + (uint64_t)(y[4] * y[4]) +
+                                            (uint64_t)(y[5] * y[5]);
+                        if (c2 <= cut) {
+                            if (at < capacity) {
+                                list_k[at] = k;
+                                list_chi2[at] = c2;
+                                list_params[at * 3 + 0] = (int32_t)y[0];
+                                list_params[at * 3 + 1] = (int32_t)y[1];
+                                list_params[at * 3 + 2] = (int32_t)y[2];
+                            }
+                            ++at;
+                        }
+                        summary->total_comb += 1;
+                    }
+    }
+    offsets[n_roads] = at;
+    summary->total_pass = at;
+    return at > capacity ? ORC_E_RANGE : ORC_OK;
 }
 
 /* Number of threads OpenMP would use (for reporting the CPU baseline). */

@@ -51,7 +51,37 @@ def brute_fit(batch, consts):
     return res
 
 
+def brute_list(batch, consts):
+    """Every passing combination, road by road in combination order, by the
+    same itertools enumeration and matrix product as brute_fit."""
+    nr = batch.n_roads
+    cut = int(consts.chi2_cut)
+    offsets, ks, chis, pars = [0], [], [], []
+    for r in range(nr):
+        n = [int(v) for v in batch.nhits[r]]
+        layers, pos = [], int(batch.hit_offsets[r])
+        for nl in n:
+            layers.append([int(v) for v in batch.hits[pos:pos + nl]])
+            pos += nl
+        combos = list(itertools.product(*[range(nl) for nl in n]))
+        if combos:
+            X = np.array([[layers[0][c[0]], layers[1][c[1]], layers[2][c[2]], layers[3][c[3]],
+                           int(batch.xft[r, 0]), int(batch.xft[r, 1])] for c in combos], np.int64)
+            s = int(batch.sector[r])
+            Y = X @ consts.coef[s].astype(np.int64).T + consts.offset[s].astype(np.int64)
+            for k in range(len(combos)):
+                c2 = sum(int(v) * int(v) for v in Y[k, 3:])
+                if c2 <= cut:
+                    ks.append(k)
+                    chis.append(c2)
+                    pars.append([int(v) for v in Y[k, :3]])
+        offsets.append(len(ks))
+    return dict(offsets=np.array(offsets, np.int64), k=np.array(ks, np.int64),
+                chi2=np.array(chis, np.uint64), params=np.array(pars, np.int64).reshape(-1, 3))
+
+
 FIELDS = ("ncomb", "npass", "best", "chi2", "params", "hit_index", "ntracks")
+LIST_FIELDS = ("offsets", "k", "chi2", "params")
 
 
 def assert_same(got: dict, want: dict, fields=FIELDS, where=""):

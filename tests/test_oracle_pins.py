@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_1311_0380_amd import synth
-from tests.pins import FIELDS, assert_same, brute_fit
+from tests.pins import FIELDS, LIST_FIELDS, assert_same, brute_fit, brute_list
 
 
 def small_constants(rng, n_sectors=72, lo=-8, hi=9):
@@ -355,3 +355,72 @@ def test_extreme_rows_exact(oracle_lib):
     coef[0, 3, :] = 0
     got, _ = run(oracle_lib, batch, synth.Constants(coef, offset, 0))
     assert got["best"][0] == 0 and got["params"][0][0] == (1 << 31) - 1
+
+
+# ---- every passing combination (the list that keeps all of them) ----------
+
+@pytest.mark.parametrize("seed", range(8))
+def test_list_passing_matches_brute_force(oracle_lib, seed):
+    """Sec. 2 on all combinations: every passing one, in road then
+    combination order, against itertools enumeration and a matrix product."""
+    rng = np.random.default_rng(2000 + seed)
+    consts = small_constants(rng)
+    batch = synth.random_small(rng, n_events=int(rng.integers(1, 6)), max_roads=4, max_hits=3,
+                               n_sectors=72)
+    consts.chi2_cut = int(rng.choice([0, 1 << 33, 1 << 35, 1 << 37, (1 << 48) - 1]))
+    rc, got, summ = oracle_lib.list_passing_batch(batch, consts)
+    assert rc == 0
+    want = brute_list(batch, consts)
+    assert_same(got, want, fields=LIST_FIELDS)
+    assert summ["total_pass"] == len(want["k"])
+
+
+def test_list_passing_agrees_with_the_fit(oracle_lib):
+    """Per road: as many entries as the fit's pass count, combination indices
+    strictly increasing, every chi2 within the cut, and the smallest
+    (chi2, k) of the entries is the fit's best."""
+    batch, consts = synth.cfg2(n_events=30)
+    rc, lst, _ = oracle_lib.list_passing_batch(batch, consts)
+    assert rc == 0
+    fit, _ = run(oracle_lib, batch, consts)
+    off = lst["offsets"]
+    assert np.array_equal(np.diff(off), fit["npass"])
+    assert np.all(lst["chi2"] <= np.uint64(consts.chi2_cut))
+    for r in range(batch.n_roads):
+        a, b = int(off[r]), int(off[r + 1])
+        if a == b:
+            assert fit["best"][r] == -1
+            continue
+        k, c2 = lst["k"][a:b], lst["chi2"][a:b]
+        assert np.all(np.diff(k) > 0) and k[0] >= 0 and k[-1] < fit["ncomb"][r]
+        j = min(range(b - a), key=lambda q: (int(c2[q]), int(k[q])))
+        assert k[j] == fit["best"][r] and c2[j] == fit["chi2"][r]
+        assert np.array_equal(lst["params"][a + j], fit["params"][r])
+
+
+def test_list_passing_everything_passes(oracle_lib):
+    """With the largest cut and small constants every combination passes:
+    road r lists k = 0 .. ncomb_r - 1."""
+    rng = np.random.default_rng(7)
+    consts = small_constants(rng)
+    consts.chi2_cut = (1 << 48) - 1
+    batch = synth.random_small(rng, n_events=5, max_roads=5, max_hits=3, n_sectors=72)
+    rc, lst, _ = oracle_lib.list_passing_batch(batch, consts)
+    assert rc == 0
+    ncomb = np.prod(batch.nhits.astype(np.int64), axis=1)
+    assert np.array_equal(np.diff(lst["offsets"]), ncomb)
+    assert np.array_equal(lst["k"], np.concatenate([np.arange(n) for n in ncomb] + [np.zeros(0, int)]))
+
+
+def test_list_passing_capacity(oracle_lib):
+    """A list that does not fit: E_RANGE, complete offsets, and the entries
+    that fit equal the start of the full list."""
+    batch, consts = synth.cfg2(n_events=10)
+    rc, full, _ = oracle_lib.list_passing_batch(batch, consts)
+    n = len(full["k"])
+    assert rc == 0 and n > 10
+    rc, part, summ = oracle_lib.list_passing_batch(batch, consts, capacity=n - 7)
+    assert rc == oracle_lib.E_RANGE and summ["total_pass"] == n
+    assert np.array_equal(part["offsets"], full["offsets"])
+    for f in ("k", "chi2", "params"):
+        assert np.array_equal(part[f], full[f][:n - 7])
