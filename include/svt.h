@@ -185,6 +185,41 @@ svt_status svt_fit_events(svt_ctx *ctx, const svt_event_batch *batch, const svt_
  */
 svt_status svt_result(svt_ctx *ctx, svt_ticket ticket, int32_t wait_us, svt_summary *out);
 
+/*
+ * Every passing combination of a batch, road by road in combination-index
+ * order (Sec. 2: the fit runs on all combinations; this keeps each one
+ * within the cut with its fit words, not only the best of its road).
+ * Device memory (SVT_MEM_DEVICE) only:
+ *   offsets [n_roads+1] int64   written: road r's entries are
+ *                               [offsets[r], offsets[r+1]) (running sum of npass)
+ *   k       [capacity]  int32   combination index in its road (layer 0 most significant)
+ *   chi2    [capacity]  uint64  its chi2 (<= cut)
+ *   params  [capacity*3] int32  its fit rows 0..2
+ */
+typedef struct {
+    int64_t *offsets;
+    int32_t *k;
+    uint64_t *chi2;
+    int32_t *params;
+    int64_t capacity;       /* entries k, chi2 and params hold (>= 0)              */
+} svt_pass_list;
+
+/*
+ * List every passing combination of `batch` (asynchronous; batch, npass and
+ * list in device memory).  npass [n_roads] int32 are the pass counts of the
+ * same batch under the loaded constants, as svt_fit_events wrote them: they
+ * place each road's entries, and roads with npass 0 are not evaluated again.
+ * Events are not read.  svt_result() then gives total_pass = entries listed
+ * (offsets[n_roads]) and total_comb = combinations evaluated; it returns
+ * SVT_E_RANGE when a road is malformed or its passing combinations differ in
+ * number from its npass (err_road = the lowest such road), or when the list
+ * exceeds capacity (err_road = -1; entries past capacity are not written).
+ * Errors returned here: SVT_E_INVAL, SVT_E_STATE (no constants), SVT_E_AGAIN,
+ * SVT_E_NOMEM, SVT_E_DEVICE.
+ */
+svt_status svt_list_passing(svt_ctx *ctx, const svt_event_batch *batch, const int32_t *npass,
+                            const svt_pass_list *list, void *hip_stream, svt_ticket *ticket);
+
 /* Static text for a status; svt_last_error() is the last HIP error text of
  * the calling thread (empty if none). */
 const char *svt_status_string(svt_status status);

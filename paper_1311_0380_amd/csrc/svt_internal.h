@@ -95,6 +95,28 @@ struct FitArgs {
     uint32_t seq;
 };
 
+// The list of every passing combination (svt_list.hip).
+struct ListArgs {
+    const uint8_t *sector;
+    const uint32_t *nhits4;
+    const int32_t *hit_offsets;
+    const int16_t *hits;
+    const uint32_t *xft2;
+    const int32_t *npass;       // pass counts of the fit, [n_roads]
+    const int64_t *offsets;     // exclusive running sum of npass, [n_roads + 1]
+    int32_t n_roads, n_hits, n_sectors;
+    const int32_t *coef;        // [n_sectors][6][6]
+    const int32_t *offset;      // [n_sectors][6]
+    uint64_t cut;
+    int32_t *k;                 // entries: combination index, chi2, fit rows 0..2
+    uint64_t *chi2;
+    int32_t *params;
+    int64_t capacity;
+    BlockPartial *partials;     // host-mapped, [gridDim.x]
+    uint32_t seq;
+};
+hipError_t launch_list(const ListArgs &a, int grid, hipStream_t stream);
+
 hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
 // start/stop non-NULL: the dispatch itself records them around the kernel
 // (no separate event packets on the stream).

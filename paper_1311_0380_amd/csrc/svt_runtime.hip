@@ -56,6 +56,7 @@ struct Slot {
     DevBuf stage;                            // device staging for host inputs / results
     DevBuf scan;                             // comb_offsets scratch
     svt_status host_status = SVT_OK;
+    int64_t list_capacity = -1;              // a passing-combination list: its capacity
 };
 
 }  // namespace
@@ -694,6 +695,75 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     return SVT_OK;
 }
 
+svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t *npass,
+                            const svt_pass_list *list, void *hip_stream, svt_ticket *ticket)
+{
+    if (c == nullptr || b == nullptr || list == nullptr || ticket == nullptr) return SVT_E_INVAL;
+    const int32_t nr = b->n_roads, nh = b->n_hits;
+    if (b->mem_kind != SVT_MEM_DEVICE || nr < 0 || nh < 0 || nr == INT32_MAX) return SVT_E_INVAL;
+    if (nr == 0 && nh != 0) return SVT_E_INVAL;
+    if (nr > 0 && (b->sector == nullptr || b->nhits == nullptr || b->hit_offsets == nullptr ||
+                   b->xft == nullptr || npass == nullptr))
+        return SVT_E_INVAL;
+    if (nh > 0 && b->hits == nullptr) return SVT_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(b->nhits) | reinterpret_cast<uintptr_t>(b->xft)) & 3u)
+        return SVT_E_INVAL;
+    if (list->offsets == nullptr || list->capacity < 0) return SVT_E_INVAL;
+    if (list->capacity > 0 && (list->k == nullptr || list->chi2 == nullptr || list->params == nullptr))
+        return SVT_E_INVAL;
+    if (!c->loaded) return SVT_E_STATE;
+    const int si = (int)(c->next_ticket % kSlots);
+    Slot &s = c->slots[si];
+    if (s.busy) return SVT_E_AGAIN;
+    DeviceGuard g(c->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
+    svt_status r = ensure(c, s.scan, svt::comb_offsets_scratch_bytes(nr));
+    if (r != SVT_OK) return r;
+
+    svt::ListArgs a;
+    memset(&a, 0, sizeof a);
+    a.sector = b->sector;
+    a.nhits4 = reinterpret_cast<const uint32_t *>(b->nhits);
+    a.hit_offsets = b->hit_offsets;
+    a.hits = b->hits;
+    a.xft2 = reinterpret_cast<const uint32_t *>(b->xft);
+    a.npass = npass;
+    a.offsets = list->offsets;
+    a.n_roads = nr;
+    a.n_hits = nh;
+    a.n_sectors = c->n_sectors;
+    a.coef = c->coef;
+    a.offset = c->offset;
+    a.cut = c->cut;
+    a.k = list->k;
+    a.chi2 = list->chi2;
+    a.params = list->params;
+    a.capacity = list->capacity;
+    a.partials = static_cast<svt::BlockPartial *>(
+        const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
+    a.seq = (uint32_t)c->next_ticket;
+    // one block per 256 roads, at most the partials' capacity
+    int64_t grid = ((int64_t)nr + svt::kBlock - 1) / svt::kBlock;
+    if (grid > c->max_grid) grid = c->max_grid;
+    if (grid < 1) grid = 1;
+
+    HIP_TRY(hipEventRecord(s.ev_start, st));
+    hipError_t e = svt::launch_comb_offsets(npass, list->offsets, nr,
+                                            static_cast<int64_t *>(s.scan.ptr), st);
+    if (e != hipSuccess) return hip_fail(e, "pass offsets launch");
+    e = svt::launch_list(a, (int)grid, st);
+    if (e != hipSuccess) return hip_fail(e, "list kernel launch");
+    HIP_TRY(hipEventRecord(s.ev_end, st));
+    s.grid = (int)grid;
+    s.parts = s.partials;
+    s.plan = nullptr;
+    s.list_capacity = list->capacity;
+    s.busy = true;
+    s.ticket = c->next_ticket++;
+    *ticket = s.ticket;
+    return SVT_OK;
+}
+
 svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *out)
 {
     if (c == nullptr || t <= 0) return SVT_E_INVAL;
@@ -734,6 +804,8 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
         status = SVT_E_DEVICE;
     } else if (er != 0xFFFFFFFFu || ee != 0xFFFFFFFFu) {
         status = SVT_E_RANGE;
+    } else if (s.list_capacity >= 0 && (int64_t)pass > s.list_capacity) {
+        status = SVT_E_RANGE;   // the list did not fit
     }
     if (out) {
         memset(out, 0, sizeof *out);
@@ -752,6 +824,7 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     if (s.plan) s.plan->busy = false;
     s.plan = nullptr;
     stage_release(c, s.stage);
+    s.list_capacity = -1;
     s.busy = false;
     s.ticket = -1;
     return status;

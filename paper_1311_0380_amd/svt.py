@@ -63,6 +63,10 @@ class svt_shadow_tracks(ctypes.Structure):
                 ("w", ctypes.c_float * 3), ("pad_", ctypes.c_int32)]
 
 
+class svt_pass_list(ctypes.Structure):
+    _fields_ = [("offsets", P), ("k", P), ("chi2", P), ("params", P), ("capacity", ctypes.c_int64)]
+
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = {
     "svt_create": (ctypes.c_int32, [ctypes.POINTER(P), ctypes.c_int32, ctypes.c_size_t]),
@@ -73,6 +77,9 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int64)]),
     "svt_result": (ctypes.c_int32, [P, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.POINTER(svt_summary)]),
+    "svt_list_passing": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch), P,
+                                          ctypes.POINTER(svt_pass_list), P,
+                                          ctypes.POINTER(ctypes.c_int64)]),
     "svt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "svt_last_error": (ctypes.c_char_p, []),
     "svt_set_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
@@ -288,6 +295,37 @@ def svt_plan_buffers(plan):
     return b, r
 
 
+def svt_list_passing(ctx, batch: svt_event_batch, npass_ptr: int, lst: svt_pass_list, stream=None):
+    t = ctypes.c_int64(0)
+    st = lib.svt_list_passing(ctx, ctypes.byref(batch), P(npass_ptr), ctypes.byref(lst),
+                              None if stream is None else P(stream), ctypes.byref(t))
+    return st, t.value
+
+
+class DevicePassList:
+    """Device buffers of a passing-combination list (torch tensors)."""
+
+    def __init__(self, n_roads: int, capacity: int, device="cuda"):
+        import torch
+        cap = max(int(capacity), 0)
+        self.capacity = cap
+        self.offsets = torch.zeros(n_roads + 1, dtype=torch.int64, device=device)
+        self.k = torch.zeros(max(cap, 1), dtype=torch.int32, device=device)
+        self.chi2 = torch.zeros(max(cap, 1), dtype=torch.int64, device=device)
+        self.params = torch.zeros((max(cap, 1), 3), dtype=torch.int32, device=device)
+
+    def struct(self) -> svt_pass_list:
+        return svt_pass_list(self.offsets.data_ptr(), self.k.data_ptr(), self.chi2.data_ptr(),
+                             self.params.data_ptr(), self.capacity)
+
+    def numpy(self, n=None) -> dict:
+        off = self.offsets.cpu().numpy()
+        n = min(int(off[-1]) if n is None else n, self.capacity)
+        return dict(offsets=off, k=self.k.cpu().numpy()[:n],
+                    chi2=self.chi2.cpu().numpy().view(np.uint64)[:n],
+                    params=self.params.cpu().numpy()[:n])
+
+
 def svt_plan_fit(plan, batch: svt_event_batch, res: svt_results, stream=None):
     t = ctypes.c_int64(0)
     st = lib.svt_plan_fit(plan, ctypes.byref(batch), ctypes.byref(res),
@@ -333,6 +371,22 @@ class Context:
         t = self.submit(dbatch.struct(), res.struct(), stream)
         st, summ = self.result(t, -1)
         return st, summ, res
+
+    def list_passing(self, dbatch: DeviceBatch, res: DeviceResults, capacity=None, stream=None):
+        """Every passing combination of a fitted device batch (res holds its
+        fit); blocks.  capacity None sizes the list from the fit's pass
+        counts.  Returns (status, summary, DevicePassList)."""
+        import torch
+        if capacity is None:
+            capacity = int(res.npass.sum().item())
+        lst = DevicePassList(dbatch.n_roads, capacity, device=dbatch.sector.device)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        st, t = svt_list_passing(self.handle, dbatch.struct(), res.npass.data_ptr(), lst.struct(),
+                                 stream)
+        check(st, "svt_list_passing")
+        st, summ = self.result(t, -1)
+        return st, summ, lst
 
     def set_tuning(self, **kw):
         check(svt_set_tuning(self.handle, **kw), "svt_set_tuning")
