@@ -1,15 +1,16 @@
 """Benchmark of the SVT linearized fit on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections fit,uneven,serve,io,shadow]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections fit,list,uneven,serve,io,shadow]
 
 Headline step = one svt_fit_events request over the scaled-up plain-fit
 workload (3000 events x 64 roads, 1-4 hits per layer, 72 sectors, lattice
 constants, half the roads with a planted track: 192,000 roads, ~7.5 M
 combinations), inputs and results resident in HBM.  Inputs rotate over
 distinct copies so timed passes read HBM rather than the 256 MB last-level
-cache.  Further sections measure the uneven-batch plan against per-event
-launches, the serving loop (p50/p99 per burst, batched against plain), the
-transfer study and the float shadow.  Prints one JSON line.
+cache.  Further sections measure the list of every passing combination,
+the uneven-batch plan against per-event launches, the serving loop (p50/p99
+per burst, batched against plain), the transfer study and the float shadow.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -147,6 +148,58 @@ def section_fit(args, svt, synth, torch):
         batch=batch, consts=consts)
     ctx.close()
     return out
+
+
+def list_algorithmic_bytes(n_roads, n_hits, entries):
+    """Bytes a passing-combination list must move: the pass counts in (4 B per
+    road), the road offsets out (8 B), the roads in (13 B: sector, hit counts,
+    hit offset, XFT words) and their hits (2 B each), and 24 B per entry
+    (index, chi2, three fit rows)."""
+    return n_roads * (4 + 8 + 13) + 2 * n_hits + 24 * entries
+
+
+def section_list(args, svt, synth, torch):
+    """Every passing combination of the 3000-event batch: one svt_list_passing
+    request after a fit, inputs and list in HBM."""
+    batch, consts = synth.cfg2()
+    ctx = svt.Context(0)
+    ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+    db = svt.to_device(batch)
+    res = svt.DeviceResults(batch.n_events, batch.n_roads)
+    st, _, _ = ctx.fit(db, res)
+    svt.check(st, "fit")
+    cap = int(res.npass.sum().item())
+    lst = svt.DevicePassList(batch.n_roads, cap)
+    b, l = db.struct(), lst.struct()
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def once():
+        st, t = svt.svt_list_passing(ctx.handle, b, res.npass.data_ptr(), l, stream)
+        svt.check(st, "svt_list_passing")
+        st, s = ctx.result(t, -1)
+        svt.check(st, "list")
+        return s
+
+    for _ in range(5):
+        once()
+    dev, wall = [], []
+    for _ in range(args.list_reps):
+        t0 = time.perf_counter()
+        s = once()
+        wall.append(time.perf_counter() - t0)
+        dev.append(s.device_ns)
+    ctx.close()
+    entries = int(s.total_pass)
+    alg = list_algorithmic_bytes(batch.n_roads, batch.n_hits, entries)
+    req_s = pct(dev, 50) * 1e-9
+    return {"workload": "every passing combination of the 3000-event x 64-road batch "
+                        "(road offsets from the fit's pass counts, then the list)",
+            "entries": entries, "combinations_evaluated": int(s.total_comb),
+            "request_device_us_p50": req_s * 1e6, "request_wall_us_p50": pct(wall, 50) * 1e6,
+            "entries_per_s": entries / req_s, "algorithmic_bytes": alg,
+            "achieved_gbs": alg / req_s / 1e9, "hbm_frac": alg / req_s / 1e9 / HBM_PEAK_GBS,
+            "timed": "events around the request: the offsets scan (three small kernels) "
+                     "and the list kernel"}
 
 
 def section_uneven(args, svt, synth, torch, uneven):
@@ -327,7 +380,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--copies", type=int, default=32)
-    ap.add_argument("--sections", default="fit,uneven,serve,io,shadow")
+    ap.add_argument("--sections", default="fit,list,uneven,serve,io,shadow")
+    ap.add_argument("--list-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--uneven-reps", type=int, default=50)
@@ -359,6 +413,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(fit["batch"], fit["consts"], args.cpu_seconds)
+    if "list" in sections:
+        log("section list")
+        line["list"] = section_list(args, svt, synth, torch)
     if "uneven" in sections:
         log("section uneven")
         line["uneven"] = section_uneven(args, svt, synth, torch, uneven)

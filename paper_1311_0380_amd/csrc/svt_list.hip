@@ -99,13 +99,17 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
             const int64_t end = ((int64_t)__builtin_amdgcn_readlane((int32_t)(o1 >> 32), j) << 32) |
                                 (uint32_t)__builtin_amdgcn_readlane((int32_t)o1, j);
             const int16_t *hp = in_lds ? s_hit + hbase : a.hits + hbase;
-            const int32_t *A = a.coef + s * 36;
-            const int32_t *B = a.offset + s * 6;
-            // constraint rows 3..5 without the layer columns
-            int32_t zc[3];
+            // the sector's rows in registers (read once per road: the
+            // entry stores below could otherwise alias them), with the XFT
+            // columns folded into each row's constant part
+            int32_t A[6][4], z[6];
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
-                zc[k] = B[3 + k] + A[(3 + k) * 6 + 4] * ya + A[(3 + k) * 6 + 5] * yb;
+            for (int k = 0; k < 6; ++k) {
+                const int32_t *row = a.coef + s * 36 + k * 6;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) A[k][l] = row[l];
+                z[k] = a.offset[s * 6 + k] + row[4] * ya + row[5] * yb;
+            }
             const uint32_t ncomb = m0 * m1 * m2 * m3;
             const uint32_t q1m = magic(m1), q2m = magic(m2), q3m = magic(m3);
             uint32_t count = 0;
@@ -124,10 +128,10 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
                 }
                 int64_t c2 = 0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    int32_t y = zc[k];
+                for (int k = 3; k < 6; ++k) {
+                    int32_t y = z[k];
 #pragma unroll
-                    for (int l = 0; l < 4; ++l) y += __mul24(A[(3 + k) * 6 + l], x[l]);
+                    for (int l = 0; l < 4; ++l) y += __mul24(A[k][l], x[l]);
                     c2 += (int64_t)y * y;
                 }
                 const bool ps = live && (uint64_t)c2 <= a.cut;
@@ -140,9 +144,9 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
                         int32_t p[3];
 #pragma unroll
                         for (int k = 0; k < 3; ++k) {
-                            int32_t y = B[k] + A[k * 6 + 4] * ya + A[k * 6 + 5] * yb;
+                            int32_t y = z[k];
 #pragma unroll
-                            for (int l = 0; l < 4; ++l) y += __mul24(A[k * 6 + l], x[l]);
+                            for (int l = 0; l < 4; ++l) y += __mul24(A[k][l], x[l]);
                             p[k] = y;
                         }
                         a.k[at] = (int32_t)t;
