@@ -7,8 +7,9 @@ numpy arrays.
 
 `fit()` wraps the plain-C nested loops in svt_oracle.c (paper Sec. 2 fit
 equation, Sec. 2.1 three nested loops); `list_passing()` keeps every passing
-combination rather than the best per road.  The float-shadow functions live
-in `oracle.shadow`.
+combination rather than the best per road; `unpack_stream()` parses the
+packed input word stream.  The float-shadow functions live in
+`oracle.shadow`.
 """
 from __future__ import annotations
 
@@ -58,6 +59,8 @@ def lib():
         L.orc_check_constants.restype = ctypes.c_int
         L.orc_check_constants.argtypes = [ctypes.c_int32, P, P, ctypes.c_uint64]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_unpack_stream.restype = ctypes.c_int
+        L.orc_unpack_stream.argtypes = [P, ctypes.c_int64] + [ctypes.c_int32] * 3 + [P] * 8
         L.orc_list_passing.restype = ctypes.c_int
         L.orc_list_passing.argtypes = [ctypes.c_int32] * 3 + [P] * 6 + [ctypes.c_int32, P, P,
                                                                        ctypes.c_uint64,
@@ -158,6 +161,32 @@ def list_passing(road_offsets, sector, nhits, hit_offsets, hits, xft, coef, offs
 def list_passing_batch(batch, consts, **kw):
     return list_passing(batch.road_offsets, batch.sector, batch.nhits, batch.hit_offsets,
                         batch.hits, batch.xft, consts.coef, consts.offset, consts.chi2_cut, **kw)
+
+
+def unpack_stream(words, max_events=None, max_roads=None, max_hits=None):
+    """Sequential parse of a packed word stream.  Returns (status, arrays,
+    counts (events, roads, hits), first bad word or -1).  Capacities default
+    to what the stream could hold at most."""
+    w = np.ascontiguousarray(words, np.uint32)
+    n = int(w.shape[0])
+    me = n if max_events is None else int(max_events)
+    mr = n if max_roads is None else int(max_roads)
+    mh = 2 * n if max_hits is None else int(max_hits)
+    out = dict(road_offsets=np.zeros(me + 1, np.int32), sector=np.zeros(max(mr, 1), np.uint8),
+               nhits=np.zeros((max(mr, 1), 4), np.uint8), hit_offsets=np.zeros(mr + 1, np.int32),
+               hits=np.zeros(max(mh, 1), np.int16), xft=np.zeros((max(mr, 1), 2), np.int16))
+    counts = np.zeros(3, np.int64)
+    bad = ctypes.c_int64(0)
+    rc = lib().orc_unpack_stream(_ptr(w), n, me, mr, mh, _ptr(out["road_offsets"]),
+                                 _ptr(out["sector"]), _ptr(out["nhits"]), _ptr(out["hit_offsets"]),
+                                 _ptr(out["hits"]), _ptr(out["xft"]), _ptr(counts),
+                                 ctypes.byref(bad))
+    ne, nr, nh = (int(v) for v in counts)
+    if rc == OK:
+        out = dict(road_offsets=out["road_offsets"][:ne + 1], sector=out["sector"][:nr],
+                   nhits=out["nhits"][:nr], hit_offsets=out["hit_offsets"][:nr + 1],
+                   hits=out["hits"][:nh], xft=out["xft"][:nr])
+    return rc, out, (ne, nr, nh), int(bad.value)
 
 
 def max_threads() -> int:

@@ -346,6 +346,125 @@ int orc_list_passing(int32_t n_events, int32_t n_roads, int32_t n_hits,
     return at > capacity ? ORC_E_RANGE : ORC_OK;
 }
 
+/*
+ * Unpack (Sec. 2.1: the first of the three stages fills the data structures
+ * from the input) of a packed word stream into the CSR batch layout.  The
+ * stream format is this project's own stand-in (the SVT format is not
+ * available): 32-bit words whose top two bits are a tag --
+ *   3 event header (bits 29..0 zero): roads up to the next event header
+ *     belong to this event;
+ *   2 road header: bits 29..22 sector, bits 19..0 the hit counts of layers
+ *     0..3 (5 bits each, layer 0 lowest, each <= 16), bits 21..20 zero;
+ *   1 XFT word: bits 11..0 and 23..12 the two XFT words, bits 29..24 zero;
+ *   0 hit word: bits 11..0 and 23..12 two hits in layer-major order (the
+ *     second zero in a road's last word when its hit count is odd), bits
+ *     29..24 zero.
+ * A road is its header, its XFT word and ceil(hits / 2) hit words; the
+ * stream starts with an event header.  A sequential parser: the first word
+ * that does not fit (or n_words when the stream ends inside a road) goes to
+ * *bad_word and the call returns ORC_E_RANGE.  counts[3] receives the
+ * events, roads and hits; a well-formed stream larger than the capacities
+ * returns ORC_E_RANGE with *bad_word = -1 (arrays then filled up to them).
+ */
+int orc_unpack_stream(const uint32_t *w, int64_t n_words, int32_t max_events, int32_t max_roads,
+                      int32_t max_hits, int32_t *road_offsets, uint8_t *sector, uint8_t *nhits,
+                      int32_t *hit_offsets, int16_t *hits, int16_t *xft, int64_t *counts,
+                      int64_t *bad_word)
+{
+    if (counts == NULL || bad_word == NULL || n_words < 0 || (n_words > 0 && w == NULL) ||
+        max_events < 0 || max_roads < 0 || max_hits < 0 || road_offsets == NULL ||
+        hit_offsets == NULL)
+        return ORC_E_INVAL;
+    int64_t ne = 0, nr = 0, nh = 0;
+    int64_t err = -1;        /* the first word that does not fit */
+    *bad_word = -1;
+    int64_t i = 0;
+    int32_t road_hits = 0;
+    while (i < n_words && err < 0) {
+        const uint32_t v = w[i];
+        const uint32_t tag = v >> 30;
+        if (tag == 3) {                                   /* event header */
+            if (v & 0x3FFFFFFFu) {
+                err = i;
+                break;
+            }
+            if (ne < max_events)
+                road_offsets[ne] = (int32_t)nr;
+            ++ne;
+            ++i;
+        } else if (tag == 2 && ne > 0) {                  /* road header, then XFT, then hits */
+            const uint32_t cnt = v & 0xFFFFFu;
+            const int n[4] = {(int)(cnt & 31u), (int)((cnt >> 5) & 31u), (int)((cnt >> 10) & 31u),
+                              (int)((cnt >> 15) & 31u)};
+            if ((v & 0x300000u) || n[0] > 16 || n[1] > 16 || n[2] > 16 || n[3] > 16) {
+                err = i;
+                break;
+            }
+            road_hits = n[0] + n[1] + n[2] + n[3];
+            if (nr < max_roads) {
+                sector[nr] = (uint8_t)((v >> 22) & 255u);
+                for (int l = 0; l < 4; ++l)
+                    nhits[nr * 4 + l] = (uint8_t)n[l];
+                hit_offsets[nr] = (int32_t)nh;
+            }
+            if (i + 1 >= n_words) {
+                err = n_words;                            /* ends before the XFT word */
+                break;
+            }
+            const uint32_t x = w[i + 1];
+            if ((x >> 30) != 1u || (x & 0x3F000000u)) {
+                err = i + 1;
+                break;
+            }
+            if (nr < max_roads) {
+                xft[nr * 2 + 0] = (int16_t)(x & 0xFFFu);
+                xft[nr * 2 + 1] = (int16_t)((x >> 12) & 0xFFFu);
+            }
+            i += 2;
+            for (int32_t j = 0; j < road_hits; j += 2) {
+                if (i >= n_words) {
+                    err = n_words;                        /* ends inside the hits */
+                    break;
+                }
+                const uint32_t h = w[i];
+                const int two = j + 1 < road_hits;
+                if ((h >> 30) != 0u || (h & 0x3F000000u) || (!two && (h & 0xFFF000u))) {
+                    err = i;
+                    break;
+                }
+                if (nh + j < max_hits)
+                    hits[nh + j] = (int16_t)(h & 0xFFFu);
+                if (two && nh + j + 1 < max_hits)
+                    hits[nh + j + 1] = (int16_t)((h >> 12) & 0xFFFu);
+                ++i;
+            }
+            if (err >= 0)
+                break;
+            nh += road_hits;
+            ++nr;
+        } else {
+            err = i;                                      /* a word out of place */
+        }
+    }
+    if (err >= 0) {
+        *bad_word = err;
+        counts[0] = ne;
+        counts[1] = nr;
+        counts[2] = nh;
+        return ORC_E_RANGE;
+    }
+    if (ne <= max_events)
+        road_offsets[ne] = (int32_t)nr;
+    if (nr <= max_roads)
+        hit_offsets[nr] = (int32_t)nh;
+    counts[0] = ne;
+    counts[1] = nr;
+    counts[2] = nh;
+    if (ne > max_events || nr > max_roads || nh > max_hits)
+        return ORC_E_RANGE;
+    return ORC_OK;
+}
+
 /* Number of threads OpenMP would use (for reporting the CPU baseline). */
 int orc_max_threads(void)
 {

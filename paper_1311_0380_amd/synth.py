@@ -142,6 +142,50 @@ def concat(batches) -> Batch:
 # --------------------------------------------------------------------------
 # constants
 # --------------------------------------------------------------------------
+# ---- packed word stream ------------------------------------------------------
+# A self-defined stand-in for the raw input the paper's unpack step reads
+# (the SVT word format itself is not available).  32-bit words, the top two
+# bits a tag:
+#   3 event header : bits 29..0 zero; the roads up to the next event header
+#                    belong to this event
+#   2 road header  : bits 29..22 sector, bits 19..0 the hit counts of layers
+#                    0..3 (5 bits each, layer 0 lowest), bits 21..20 zero
+#   1 XFT word     : bits 11..0 first XFT word, bits 23..12 second, 29..24 zero
+#   0 hit word     : two hits of the road (layer-major order), bits 11..0 the
+#                    first, bits 23..12 the second (zero in a road's last word
+#                    when its hit count is odd), bits 29..24 zero
+# A road is its header, its XFT word and ceil(hits / 2) hit words.
+STREAM_HIT, STREAM_XFT, STREAM_ROAD, STREAM_EVENT = 0, 1, 2, 3
+
+
+def pack_stream(batch: "Batch") -> np.ndarray:
+    """The batch as a packed word stream (uint32)."""
+    ne, nr = batch.n_events, batch.n_roads
+    nh = batch.nhits.astype(np.int64).reshape(nr, 4)
+    tot = nh.sum(axis=1)
+    length = 2 + (tot + 1) // 2                        # words per road
+    ro = batch.road_offsets.astype(np.int64)
+    cl = np.concatenate([[0], np.cumsum(length)])
+    ev_words = 1 + cl[ro[1:]] - cl[ro[:-1]]
+    ev_start = np.concatenate([[0], np.cumsum(ev_words)])
+    words = np.zeros(int(ev_start[-1]), np.uint32)
+    words[ev_start[:-1]] = np.uint32(STREAM_EVENT << 30)
+    ev_of_road = np.repeat(np.arange(ne), np.diff(ro))
+    road_start = ev_start[ev_of_road] + 1 + cl[:-1] - cl[ro[ev_of_road]]
+    counts = nh[:, 0] | (nh[:, 1] << 5) | (nh[:, 2] << 10) | (nh[:, 3] << 15)
+    words[road_start] = ((STREAM_ROAD << 30) | (batch.sector.astype(np.int64) << 22) |
+                         counts).astype(np.uint32)
+    xf = batch.xft.astype(np.int64).reshape(nr, 2)
+    words[road_start + 1] = ((STREAM_XFT << 30) | (xf[:, 1] << 12) | xf[:, 0]).astype(np.uint32)
+    ho = batch.hit_offsets.astype(np.int64)
+    road_of_hit = np.repeat(np.arange(nr), np.diff(ho))
+    j = np.arange(batch.n_hits) - ho[road_of_hit]
+    widx = road_start[road_of_hit] + 2 + j // 2
+    val = (batch.hits.astype(np.int64) << (12 * (j % 2))).astype(np.uint32)
+    np.bitwise_or.at(words, widx, val)
+    return words
+
+
 def uniform_constants(rng: np.random.Generator, n_sectors=N_SECTORS, lo=-1024, hi=1024,
                       chi2_cut=CUT_CFG1) -> Constants:
     """Constants drawn uniformly from [lo, hi) (the small plain-fit workload)."""
