@@ -220,6 +220,48 @@ typedef struct {
 svt_status svt_list_passing(svt_ctx *ctx, const svt_event_batch *batch, const int32_t *npass,
                             const svt_pass_list *list, void *hip_stream, svt_ticket *ticket);
 
+/*
+ * Packed input word stream (this library's own format; the paper's unpack
+ * stage, Sec. 2.1, reads the experiment's raw words, whose format is not
+ * given).  32-bit words, the top two bits a tag:
+ *   3 event header  bits 29..0 zero; the roads up to the next event header
+ *                   belong to it
+ *   2 road header   bits 29..22 sector, bits 19..0 the hit counts of layers
+ *                   0..3 (5 bits each, layer 0 lowest, each <= 16), 21..20 zero
+ *   1 XFT word      bits 11..0 first XFT word, 23..12 second, 29..24 zero
+ *   0 hit word      two hits in layer-major order, bits 11..0 the first and
+ *                   23..12 the second (zero in a road's last word when its
+ *                   hit count is odd), bits 29..24 zero
+ * A road is its header, its XFT word and ceil(hits / 2) hit words; the
+ * stream starts with an event header.
+ */
+typedef struct {
+    int32_t *road_offsets;  /* [max_events+1]  as in svt_event_batch           */
+    uint8_t *sector;        /* [max_roads]                                      */
+    uint8_t *nhits;         /* [max_roads*4], 4-byte aligned                    */
+    int32_t *hit_offsets;   /* [max_roads+1]                                    */
+    int16_t *hits;          /* [max_hits]                                       */
+    int16_t *xft;           /* [max_roads*2], 4-byte aligned                    */
+    int32_t max_events, max_roads, max_hits, pad_;
+} svt_unpack_out;
+
+/*
+ * Unpack a word stream into the batch arrays of `out` (device memory), ready
+ * for svt_fit_events (asynchronous).  mem_kind says where `words` lives:
+ * SVT_MEM_DEVICE (read in place), SVT_MEM_MAPPED (read in place over the
+ * bus: zero copy), SVT_MEM_PINNED or SVT_MEM_PAGEABLE (copied to device
+ * staging first).  n_words <= (16 * compute units - 1) * 4096 (16,773,120 on
+ * 256 compute units).
+ * svt_result() then gives the batch's size in the summary -- total_tracks =
+ * events, total_comb = roads, total_pass = hits -- and returns SVT_E_RANGE
+ * when the stream breaks the format (err_road = the index of the first word
+ * out of place, n_words if it ends inside a road; the arrays are then
+ * unspecified) or when the batch exceeds a capacity (err_road = -1).
+ * Errors returned here: SVT_E_INVAL, SVT_E_AGAIN, SVT_E_NOMEM, SVT_E_DEVICE.
+ */
+svt_status svt_unpack_stream(svt_ctx *ctx, const uint32_t *words, int64_t n_words, int32_t mem_kind,
+                             const svt_unpack_out *out, void *hip_stream, svt_ticket *ticket);
+
 /* Static text for a status; svt_last_error() is the last HIP error text of
  * the calling thread (empty if none). */
 const char *svt_status_string(svt_status status);

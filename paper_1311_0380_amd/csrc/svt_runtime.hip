@@ -57,6 +57,8 @@ struct Slot {
     DevBuf scan;                             // comb_offsets scratch
     svt_status host_status = SVT_OK;
     int64_t list_capacity = -1;              // a passing-combination list: its capacity
+    bool unpack = false;                     // a stream unpack: its capacities
+    int64_t unpack_cap[3] = {0, 0, 0};
 };
 
 }  // namespace
@@ -764,6 +766,91 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     return SVT_OK;
 }
 
+svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words, int32_t mem_kind,
+                             const svt_unpack_out *out, void *hip_stream, svt_ticket *ticket)
+{
+    if (c == nullptr || out == nullptr || ticket == nullptr || !kind_ok(mem_kind)) return SVT_E_INVAL;
+    if (n_words < 0 || (n_words > 0 && words == nullptr)) return SVT_E_INVAL;
+    if (n_words > svt::unpack_max_words(c->max_grid)) return SVT_E_INVAL;
+    if (out->max_events < 0 || out->max_roads < 0 || out->max_hits < 0) return SVT_E_INVAL;
+    if (out->road_offsets == nullptr || out->hit_offsets == nullptr) return SVT_E_INVAL;
+    if (out->max_roads > 0 && (out->sector == nullptr || out->nhits == nullptr || out->xft == nullptr))
+        return SVT_E_INVAL;
+    if (out->max_hits > 0 && out->hits == nullptr) return SVT_E_INVAL;
+    if ((reinterpret_cast<uintptr_t>(out->nhits) | reinterpret_cast<uintptr_t>(out->xft)) & 3u)
+        return SVT_E_INVAL;
+    const int si = (int)(c->next_ticket % kSlots);
+    Slot &s = c->slots[si];
+    if (s.busy) return SVT_E_AGAIN;
+    DeviceGuard g(c->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
+
+    // staging: the tile sums, then the words when they are not in device memory
+    const bool in_device = mem_kind == SVT_MEM_DEVICE;
+    const size_t b_tiles = align_up(svt::unpack_scratch_bytes(n_words), 256);
+    const size_t need = b_tiles + (in_device ? 0 : align_up(4 * (size_t)n_words, 256));
+    svt_status r = stage_acquire(c, s.stage, need);
+    if (r != SVT_OK) return r;
+    struct StageGuard {
+        svt_ctx *c;
+        DevBuf *b;
+        bool keep = false;
+        ~StageGuard()
+        {
+            if (!keep) stage_release(c, *b);
+        }
+    } guard{c, &s.stage};
+    char *base = static_cast<char *>(s.stage.ptr);
+
+    svt::UnpackArgs a;
+    memset(&a, 0, sizeof a);
+    a.n_words = n_words;
+    a.tiles = reinterpret_cast<svt::UnpackAgg *>(base);
+    uint32_t *dev_words = in_device ? const_cast<uint32_t *>(words)
+                                    : reinterpret_cast<uint32_t *>(base + b_tiles);
+    a.words = dev_words;
+    a.src = dev_words;
+    a.copy = 0;
+    a.road_offsets = out->road_offsets;
+    a.sector = out->sector;
+    a.nhits4 = reinterpret_cast<uint32_t *>(out->nhits);
+    a.hit_offsets = out->hit_offsets;
+    a.hits = out->hits;
+    a.xft2 = reinterpret_cast<uint32_t *>(out->xft);
+    a.max_events = out->max_events;
+    a.max_roads = out->max_roads;
+    a.max_hits = out->max_hits;
+    a.n_apply = (int32_t)svt::unpack_tiles(n_words);
+    a.partials = static_cast<svt::BlockPartial *>(
+        const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
+    a.seq = (uint32_t)c->next_ticket;
+
+    HIP_TRY(hipEventRecord(s.ev_start, st));
+    if (mem_kind == SVT_MEM_MAPPED) {
+        // zero copy: the first pass reads the host words in place and leaves
+        // a device copy for the others
+        a.src = static_cast<const uint32_t *>(device_view(words, mem_kind));
+        a.copy = 1;
+    } else if (!in_device && n_words > 0) {
+        HIP_TRY(hipMemcpyAsync(dev_words, words, 4 * (size_t)n_words, hipMemcpyHostToDevice, st));
+    }
+    hipError_t e = svt::launch_unpack(a, st);
+    if (e != hipSuccess) return hip_fail(e, "unpack launch");
+    HIP_TRY(hipEventRecord(s.ev_end, st));
+    guard.keep = true;
+    s.grid = a.n_apply + 1;
+    s.parts = s.partials;
+    s.plan = nullptr;
+    s.unpack = true;
+    s.unpack_cap[0] = out->max_events;
+    s.unpack_cap[1] = out->max_roads;
+    s.unpack_cap[2] = out->max_hits;
+    s.busy = true;
+    s.ticket = c->next_ticket++;
+    *ticket = s.ticket;
+    return SVT_OK;
+}
+
 svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *out)
 {
     if (c == nullptr || t <= 0) return SVT_E_INVAL;
@@ -806,6 +893,9 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
         status = SVT_E_RANGE;
     } else if (s.list_capacity >= 0 && (int64_t)pass > s.list_capacity) {
         status = SVT_E_RANGE;   // the list did not fit
+    } else if (s.unpack && ((int64_t)trk > s.unpack_cap[0] || (int64_t)comb > s.unpack_cap[1] ||
+                            (int64_t)pass > s.unpack_cap[2])) {
+        status = SVT_E_RANGE;   // the batch did not fit
     }
     if (out) {
         memset(out, 0, sizeof *out);
@@ -825,6 +915,7 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     s.plan = nullptr;
     stage_release(c, s.stage);
     s.list_capacity = -1;
+    s.unpack = false;
     s.busy = false;
     s.ticket = -1;
     return status;

@@ -1,0 +1,245 @@
+// Unpack of a packed input word stream into the CSR batch (arXiv:1311.0380,
+// Sec. 2.1: the first of the three stages fills the data structures from
+// the input).  The word format is this library's own (include/svt.h): tagged
+// 32-bit words -- event header, road header (sector, hit counts), XFT word,
+// hit words of two hits.
+//
+// Every word's place in the batch follows from counts over the words before
+// it, so the unpack is three data-parallel passes instead of a sequential
+// parse:
+//   tile_reduce  per tile of 4096 words: event headers, road headers, hits
+//                declared by road headers, last road header, last event
+//                header (and a copy of the words into device memory when
+//                they are read from host-mapped memory);
+//   tile_scan    one block: the same quantities before each tile, the
+//                totals, the end-of-stream check, the final offsets;
+//   tile_apply   per word: its event / road / hit index from the tile's
+//                prefix plus a block scan, the checks that a sequential
+//                parser would make at that word, and the writes.
+// The first word that breaks the format is the smallest flagged word: up to
+// it the stream is well formed, so every count there equals the parser's.
+#include "svt_internal.h"
+
+namespace svt {
+namespace {
+
+constexpr int kPer = 16;                       // words per thread
+constexpr int kTile = kBlock * kPer;           // words per tile
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// sums and last positions (-1 if none) over a range of words
+using Agg = UnpackAgg;
+
+__device__ __forceinline__ uint32_t tag_of(uint32_t w) { return w >> 30; }
+__device__ __forceinline__ uint32_t road_hits(uint32_t w)
+{
+    const uint32_t c = w & 0xFFFFFu;
+    return (c & 31u) + ((c >> 5) & 31u) + ((c >> 10) & 31u) + ((c >> 15) & 31u);
+}
+// words of a road: header, XFT word, ceil(hits / 2) hit words
+__device__ __forceinline__ int64_t road_len(uint32_t header) { return 2 + (road_hits(header) + 1) / 2; }
+
+__device__ __forceinline__ Agg agg_word(uint32_t w, int64_t pos)
+{
+    const uint32_t t = tag_of(w);
+    Agg a;
+    a.ev = t == 3u;
+    a.rd = t == 2u;
+    a.hits = t == 2u ? road_hits(w) : 0;
+    a.last_road = t == 2u ? pos : -1;
+    a.last_ev = t == 3u ? pos : -1;
+    return a;
+}
+
+__device__ __forceinline__ Agg agg_add(const Agg &x, const Agg &y)
+{
+    return Agg{x.ev + y.ev, x.rd + y.rd, x.hits + y.hits, max(x.last_road, y.last_road),
+               max(x.last_ev, y.last_ev)};
+}
+
+// Exclusive scan of one Agg per thread across the block (thread order), and
+// the block total.  Wavefront shuffles, then the wavefront totals in LDS.
+__device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    Agg incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        Agg o;
+        o.ev = __shfl_up(incl.ev, off, 64);
+        o.rd = __shfl_up(incl.rd, off, 64);
+        o.hits = __shfl_up(incl.hits, off, 64);
+        o.last_road = __shfl_up(incl.last_road, off, 64);
+        o.last_ev = __shfl_up(incl.last_ev, off, 64);
+        if (lane >= off) incl = agg_add(o, incl);
+    }
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    Agg before{0, 0, 0, -1, -1};
+    Agg tot{0, 0, 0, -1, -1};
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wid) before = agg_add(before, s_w[w]);
+        tot = agg_add(tot, s_w[w]);
+    }
+    __syncthreads();
+    total = tot;
+    // exclusive = before + (inclusive of this lane's predecessors)
+    Agg prev;
+    prev.ev = __shfl_up(incl.ev, 1, 64);
+    prev.rd = __shfl_up(incl.rd, 1, 64);
+    prev.hits = __shfl_up(incl.hits, 1, 64);
+    prev.last_road = __shfl_up(incl.last_road, 1, 64);
+    prev.last_ev = __shfl_up(incl.last_ev, 1, 64);
+    if (lane == 0) prev = Agg{0, 0, 0, -1, -1};
+    return agg_add(before, prev);
+}
+
+__global__ void __launch_bounds__(kBlock) tile_reduce(UnpackArgs a)
+{
+    __shared__ Agg s_w[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
+    Agg acc{0, 0, 0, -1, -1};
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int64_t p = base + i;
+        if (p < a.n_words) {
+            const uint32_t w = a.src[p];
+            if (a.copy) a.words[p] = w;
+            acc = agg_add(acc, agg_word(w, p));
+        }
+    }
+    Agg tot;
+    (void)block_excl(acc, s_w, tot);
+    if (threadIdx.x == 0) a.tiles[blockIdx.x] = tot;
+}
+
+// One block: tile prefixes, totals, the end-of-stream check, final offsets.
+__global__ void __launch_bounds__(kBlock) tile_scan(UnpackArgs a, int32_t n_tiles)
+{
+    __shared__ Agg s_w[kBlock / 64];
+    Agg carry{0, 0, 0, -1, -1};
+    for (int32_t t0 = 0; t0 < n_tiles; t0 += kBlock) {
+        const int32_t t = t0 + (int32_t)threadIdx.x;
+        const Agg v = t < n_tiles ? a.tiles[t] : Agg{0, 0, 0, -1, -1};
+        Agg tot;
+        const Agg ex = block_excl(v, s_w, tot);
+        if (t < n_tiles) a.tiles[t] = agg_add(carry, ex);
+        carry = agg_add(carry, tot);
+    }
+    if (threadIdx.x == 0) {
+        // the stream must end where its last road ends (or right after an
+        // event header that has no road)
+        uint32_t bad = kNone;
+        const int64_t W = a.n_words;
+        if (W > 0) {
+            const int64_t end = carry.last_road > carry.last_ev
+                                    ? carry.last_road + road_len(a.words[carry.last_road])
+                                    : carry.last_ev + 1;
+            if (end != W) bad = (uint32_t)W;
+        }
+        if (carry.ev <= a.max_events) a.road_offsets[carry.ev] = (int32_t)carry.rd;
+        if (carry.rd <= a.max_roads) a.hit_offsets[carry.rd] = (int32_t)carry.hits;
+        a.partials[a.n_apply] = BlockPartial{(uint64_t)carry.rd, (uint64_t)carry.hits,
+                                             (uint32_t)carry.ev, bad, kNone, a.seq};
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a)
+{
+    __shared__ Agg s_w[kBlock / 64];
+    __shared__ uint32_t s_bad[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
+    uint32_t w[kPer];
+    Agg acc{0, 0, 0, -1, -1};
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int64_t p = base + i;
+        w[i] = p < a.n_words ? a.words[p] : 0u;
+        if (p < a.n_words) acc = agg_add(acc, agg_word(w[i], p));
+    }
+    Agg tot;
+    Agg pre = agg_add(a.tiles[blockIdx.x], block_excl(acc, s_w, tot));
+    uint32_t bad = kNone;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int64_t p = base + i;
+        if (p >= a.n_words) break;
+        const uint32_t v = w[i], t = tag_of(v);
+        // pre holds the counts over the words before p
+        const int64_t P = pre.last_road, Q = pre.last_ev;
+        bool ok = true;
+        if (t == 3u || t == 2u) {
+            // a header: the previous road of this event ends here, or the
+            // event header that opens it is the word before
+            const int64_t expect = P > Q ? P + road_len(a.words[P]) : Q + 1;
+            ok = (p == 0 && t == 3u) || (Q >= 0 && p == expect);
+        }
+        if (t == 3u) {
+            ok = ok && (v & 0x3FFFFFFFu) == 0u;
+            if (pre.ev < a.max_events) a.road_offsets[pre.ev] = (int32_t)pre.rd;
+        } else if (t == 2u) {
+            const uint32_t c = v & 0xFFFFFu;
+            ok = ok && (v & 0x300000u) == 0u && (c & 31u) <= 16u && ((c >> 5) & 31u) <= 16u &&
+                 ((c >> 10) & 31u) <= 16u && ((c >> 15) & 31u) <= 16u;
+            if (pre.rd < a.max_roads) {
+                const int64_t r = pre.rd;
+                a.sector[r] = (uint8_t)((v >> 22) & 255u);
+                a.nhits4[r] = (c & 31u) | (((c >> 5) & 31u) << 8) | (((c >> 10) & 31u) << 16) |
+                              (((c >> 15) & 31u) << 24);
+                a.hit_offsets[r] = (int32_t)pre.hits;
+            }
+        } else {
+            // XFT or hit word of the road whose header is at P
+            ok = P > Q && (v & 0x3F000000u) == 0u;
+            if (ok) {
+                const uint32_t hdr = a.words[P];
+                const int64_t r = pre.rd - 1;
+                if (t == 1u) {
+                    ok = p == P + 1;
+                    if (ok && r < a.max_roads) a.xft2[r] = (v & 0xFFFu) | (((v >> 12) & 0xFFFu) << 16);
+                } else {
+                    const int64_t S = road_hits(hdr);
+                    const int64_t j = 2 * (p - P - 2);
+                    ok = p >= P + 2 && p < P + road_len(hdr) && (j + 1 < S || (v & 0xFFF000u) == 0u);
+                    if (ok) {
+                        const int64_t h = pre.hits - S + j;   // pre.hits counts this road's hits
+                        if (h < a.max_hits) a.hits[h] = (int16_t)(v & 0xFFFu);
+                        if (j + 1 < S && h + 1 < a.max_hits) a.hits[h + 1] = (int16_t)((v >> 12) & 0xFFFu);
+                    }
+                }
+            }
+        }
+        if (!ok) bad = min(bad, (uint32_t)p);
+        pre = agg_add(pre, agg_word(v, p));
+    }
+    // lowest flagged word of the block -> host-mapped partials
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bad = min(bad, (uint32_t)__shfl_xor((int)bad, off, 64));
+    if ((threadIdx.x & 63) == 0) s_bad[threadIdx.x >> 6] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = s_bad[0];
+        for (int i = 1; i < kBlock / 64; ++i) b = min(b, s_bad[i]);
+        a.partials[blockIdx.x] = BlockPartial{0, 0, 0, b, kNone, a.seq};
+    }
+}
+
+}  // namespace
+
+int64_t unpack_tiles(int64_t n_words) { return (n_words + kTile - 1) / kTile; }
+
+size_t unpack_scratch_bytes(int64_t n_words) { return (size_t)(unpack_tiles(n_words) + 1) * sizeof(Agg); }
+
+int64_t unpack_max_words(int max_partials) { return (int64_t)(max_partials - 1) * kTile; }
+
+hipError_t launch_unpack(UnpackArgs a, hipStream_t stream)
+{
+    const int64_t tiles = unpack_tiles(a.n_words);
+    if (tiles > 0) hipLaunchKernelGGL(tile_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL(tile_scan, dim3(1), dim3(kBlock), 0, stream, a, (int32_t)tiles);
+    if (tiles > 0) hipLaunchKernelGGL(tile_apply, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace svt

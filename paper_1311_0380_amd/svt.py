@@ -67,6 +67,12 @@ class svt_pass_list(ctypes.Structure):
     _fields_ = [("offsets", P), ("k", P), ("chi2", P), ("params", P), ("capacity", ctypes.c_int64)]
 
 
+class svt_unpack_out(ctypes.Structure):
+    _fields_ = [("road_offsets", P), ("sector", P), ("nhits", P), ("hit_offsets", P), ("hits", P),
+                ("xft", P), ("max_events", ctypes.c_int32), ("max_roads", ctypes.c_int32),
+                ("max_hits", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
 # (name, restype, argtypes) of every exported entry point
 SIGNATURES = {
     "svt_create": (ctypes.c_int32, [ctypes.POINTER(P), ctypes.c_int32, ctypes.c_size_t]),
@@ -80,6 +86,9 @@ SIGNATURES = {
     "svt_list_passing": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch), P,
                                           ctypes.POINTER(svt_pass_list), P,
                                           ctypes.POINTER(ctypes.c_int64)]),
+    "svt_unpack_stream": (ctypes.c_int32, [P, P, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.POINTER(svt_unpack_out), P,
+                                           ctypes.POINTER(ctypes.c_int64)]),
     "svt_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "svt_last_error": (ctypes.c_char_p, []),
     "svt_set_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
@@ -302,6 +311,39 @@ def svt_list_passing(ctx, batch: svt_event_batch, npass_ptr: int, lst: svt_pass_
     return st, t.value
 
 
+def svt_unpack_stream(ctx, words_ptr: int, n_words: int, mem_kind: int, out: svt_unpack_out,
+                      stream=None):
+    t = ctypes.c_int64(0)
+    st = lib.svt_unpack_stream(ctx, None if not words_ptr else P(words_ptr), int(n_words),
+                               int(mem_kind), ctypes.byref(out),
+                               None if stream is None else P(stream), ctypes.byref(t))
+    return st, t.value
+
+
+class DeviceUnpacked:
+    """Device arrays (torch tensors) an unpack fills, at given capacities."""
+
+    def __init__(self, max_events: int, max_roads: int, max_hits: int, device="cuda"):
+        import torch
+        self.caps = (int(max_events), int(max_roads), int(max_hits))
+        z = lambda n, dt: torch.zeros(n, dtype=dt, device=device)
+        self.road_offsets = z(max_events + 1, torch.int32)
+        self.sector = z(max(max_roads, 1), torch.uint8)
+        self.nhits = z((max(max_roads, 1), 4), torch.uint8)
+        self.hit_offsets = z(max_roads + 1, torch.int32)
+        self.hits = z(max(max_hits, 1), torch.int16)
+        self.xft = z((max(max_roads, 1), 2), torch.int16)
+
+    def struct(self) -> svt_unpack_out:
+        return svt_unpack_out(*[getattr(self, f).data_ptr() for f in BATCH_FIELDS], *self.caps, 0)
+
+    def batch(self, n_events: int, n_roads: int, n_hits: int) -> "DeviceBatch":
+        """The unpacked batch (views of the leading entries)."""
+        return DeviceBatch(road_offsets=self.road_offsets[:n_events + 1], sector=self.sector[:n_roads],
+                           nhits=self.nhits[:n_roads], hit_offsets=self.hit_offsets[:n_roads + 1],
+                           hits=self.hits[:n_hits], xft=self.xft[:n_roads])
+
+
 class DevicePassList:
     """Device buffers of a passing-combination list (torch tensors)."""
 
@@ -387,6 +429,33 @@ class Context:
         check(st, "svt_list_passing")
         st, summ = self.result(t, -1)
         return st, summ, lst
+
+    def unpack_stream(self, words, mem_kind=None, caps=None, stream=None):
+        """Unpack a packed word stream (a torch tensor of int32/uint32 words on
+        the device or in pinned host memory, or a numpy array); blocks.
+        caps = (max_events, max_roads, max_hits), by default the most the
+        stream could hold.  Returns (status, summary, DeviceBatch or None)."""
+        import torch
+        if isinstance(words, np.ndarray):
+            host = torch.from_numpy(np.ascontiguousarray(words).view(np.int32))
+            kind = SVT_MEM_PAGEABLE if mem_kind is None else mem_kind
+            ptr, n = host.data_ptr(), host.numel()
+        else:
+            host = words
+            kind = (SVT_MEM_DEVICE if words.is_cuda else SVT_MEM_MAPPED) if mem_kind is None else mem_kind
+            ptr, n = words.data_ptr(), words.numel()
+        if caps is None:
+            caps = (n, n // 2, 2 * n)
+        out = DeviceUnpacked(*caps)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        st, t = svt_unpack_stream(self.handle, ptr, n, kind, out.struct(), stream)
+        check(st, "svt_unpack_stream")
+        st, summ = self.result(t, -1)
+        del host
+        if st != SVT_OK:
+            return st, summ, None
+        return st, summ, out.batch(summ.total_tracks, int(summ.total_comb), int(summ.total_pass))
 
     def set_tuning(self, **kw):
         check(svt_set_tuning(self.handle, **kw), "svt_set_tuning")

@@ -56,7 +56,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     structs = {"svt_event_batch": svt.svt_event_batch, "svt_results": svt.svt_results,
                "svt_summary": svt.svt_summary, "svt_tuning": svt.svt_tuning,
                "svt_device_info": svt.svt_device_info,
-               "svt_shadow_tracks": svt.svt_shadow_tracks, "svt_pass_list": svt.svt_pass_list}
+               "svt_shadow_tracks": svt.svt_shadow_tracks, "svt_pass_list": svt.svt_pass_list,
+               "svt_unpack_out": svt.svt_unpack_out}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "svt.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
