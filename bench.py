@@ -1,6 +1,7 @@
 """Benchmark of the SVT linearized fit on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--sections fit,list,uneven,serve,io,shadow]
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+                [--sections fit,list,unpack,uneven,serve,io,shadow]
 
 Headline step = one svt_fit_events request over the scaled-up plain-fit
 workload (3000 events x 64 roads, 1-4 hits per layer, 72 sectors, lattice
@@ -8,7 +9,7 @@ constants, half the roads with a planted track: 192,000 roads, ~7.5 M
 combinations), inputs and results resident in HBM.  Inputs rotate over
 distinct copies so timed passes read HBM rather than the 256 MB last-level
 cache.  Further sections measure the list of every passing combination,
-the uneven-batch plan against per-event launches, the serving loop (p50/p99
+the unpack of a packed word stream, the uneven-batch plan against per-event launches, the serving loop (p50/p99
 per burst, batched against plain), the transfer study and the float shadow.
 Prints one JSON line.
 """
@@ -202,6 +203,56 @@ def section_list(args, svt, synth, torch):
                      "and the list kernel"}
 
 
+def section_unpack(args, svt, synth, torch):
+    """Unpack of the 3000-event batch's packed word stream into the CSR
+    batch: from device memory, from host-mapped memory read in place (zero
+    copy) and from pageable memory (DMA copy first); then unpack + fit from
+    host-mapped memory."""
+    batch, consts = synth.cfg2()
+    words = synth.pack_stream(batch)
+    ctx = svt.Context(0)
+    ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+    caps = (batch.n_events, batch.n_roads, batch.n_hits)
+    w32 = torch.from_numpy(words.view(np.int32))
+    srcs = {"device": (w32.cuda(), svt.SVT_MEM_DEVICE), "mapped": (w32.pin_memory(), svt.SVT_MEM_MAPPED),
+            "pageable": (words, svt.SVT_MEM_PAGEABLE)}
+    out_bytes = 4 * (batch.n_events + 1) + 13 * batch.n_roads + 4 + 2 * batch.n_hits
+    in_bytes = 4 * len(words)
+    res = {"workload": "the 3000-event x 64-road batch as a packed word stream "
+                       f"({len(words)} words, {in_bytes} B) unpacked into the CSR batch ({out_bytes} B)",
+           "words": len(words), "stream_bytes": in_bytes, "batch_bytes": out_bytes}
+    for name, (src, kind) in srcs.items():
+        for _ in range(3):
+            st, s, _ = ctx.unpack_stream(src, mem_kind=kind, caps=caps)
+            svt.check(st, "unpack")
+        dev, wall = [], []
+        for _ in range(args.unpack_reps):
+            t0 = time.perf_counter()
+            st, s, _ = ctx.unpack_stream(src, mem_kind=kind, caps=caps)
+            wall.append(time.perf_counter() - t0)
+            dev.append(s.device_ns)
+        d = pct(dev, 50) * 1e-9
+        res[name] = {"request_device_us_p50": d * 1e6, "request_wall_us_p50": pct(wall, 50) * 1e6,
+                     "gbs": (in_bytes + out_bytes) / d / 1e9}
+    # ingest: unpack from host-mapped words, then fit the unpacked batch
+    src, kind = srcs["mapped"]
+    dres = svt.DeviceResults(batch.n_events, batch.n_roads)
+    wall = []
+    for i in range(args.unpack_reps + 3):
+        t0 = time.perf_counter()
+        st, s, db = ctx.unpack_stream(src, mem_kind=kind, caps=caps)
+        svt.check(st, "unpack")
+        st, fs, _ = ctx.fit(db, dres)
+        svt.check(st, "fit")
+        if i >= 3:
+            wall.append(time.perf_counter() - t0)
+    res["mapped_unpack_then_fit_wall_us_p50"] = pct(wall, 50) * 1e6
+    ctx.close()
+    res["timed"] = ("device time: events around the request (three passes over the words, plus the "
+                    "DMA copy for pageable words)")
+    return res
+
+
 def section_uneven(args, svt, synth, torch, uneven):
     batch, consts = synth.cfg3()
     ctx = svt.Context(0)
@@ -380,8 +431,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--copies", type=int, default=32)
-    ap.add_argument("--sections", default="fit,list,uneven,serve,io,shadow")
+    ap.add_argument("--sections", default="fit,list,unpack,uneven,serve,io,shadow")
     ap.add_argument("--list-reps", type=int, default=50)
+    ap.add_argument("--unpack-reps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--uneven-reps", type=int, default=50)
@@ -416,6 +468,9 @@ def main():
     if "list" in sections:
         log("section list")
         line["list"] = section_list(args, svt, synth, torch)
+    if "unpack" in sections:
+        log("section unpack")
+        line["unpack"] = section_unpack(args, svt, synth, torch)
     if "uneven" in sections:
         log("section uneven")
         line["uneven"] = section_uneven(args, svt, synth, torch, uneven)

@@ -250,8 +250,7 @@ typedef struct {
  * for svt_fit_events (asynchronous).  mem_kind says where `words` lives:
  * SVT_MEM_DEVICE (read in place), SVT_MEM_MAPPED (read in place over the
  * bus: zero copy), SVT_MEM_PINNED or SVT_MEM_PAGEABLE (copied to device
- * staging first).  n_words <= (16 * compute units - 1) * 4096 (16,773,120 on
- * 256 compute units).
+ * staging first).  n_words < 2^31.
  * svt_result() then gives the batch's size in the summary -- total_tracks =
  * events, total_comb = roads, total_pass = hits -- and returns SVT_E_RANGE
  * when the stream breaks the format (err_road = the index of the first word

@@ -135,13 +135,15 @@ struct UnpackArgs {
     int16_t *hits;
     uint32_t *xft2;
     int32_t max_events, max_roads, max_hits;
-    int32_t n_apply;            // blocks of the last pass; the scan's partial follows theirs
+    int32_t n_apply;            // blocks of the last pass (a grid-stride loop over the
+                                // tiles); the scan's partial follows theirs
     BlockPartial *partials;     // host-mapped, [n_apply + 1]
     uint32_t seq;
 };
 int64_t unpack_tiles(int64_t n_words);
 size_t unpack_scratch_bytes(int64_t n_words);
-int64_t unpack_max_words(int max_partials);
+int64_t unpack_max_words();
+int32_t unpack_apply_blocks(int64_t n_words, int max_partials);
 hipError_t launch_unpack(UnpackArgs a, hipStream_t stream);
 
 hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)

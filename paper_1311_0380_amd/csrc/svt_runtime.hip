@@ -771,7 +771,7 @@ svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words,
 {
     if (c == nullptr || out == nullptr || ticket == nullptr || !kind_ok(mem_kind)) return SVT_E_INVAL;
     if (n_words < 0 || (n_words > 0 && words == nullptr)) return SVT_E_INVAL;
-    if (n_words > svt::unpack_max_words(c->max_grid)) return SVT_E_INVAL;
+    if (n_words > svt::unpack_max_words()) return SVT_E_INVAL;
     if (out->max_events < 0 || out->max_roads < 0 || out->max_hits < 0) return SVT_E_INVAL;
     if (out->road_offsets == nullptr || out->hit_offsets == nullptr) return SVT_E_INVAL;
     if (out->max_roads > 0 && (out->sector == nullptr || out->nhits == nullptr || out->xft == nullptr))
@@ -820,7 +820,7 @@ svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words,
     a.max_events = out->max_events;
     a.max_roads = out->max_roads;
     a.max_hits = out->max_hits;
-    a.n_apply = (int32_t)svt::unpack_tiles(n_words);
+    a.n_apply = svt::unpack_apply_blocks(n_words, c->max_grid);
     a.partials = static_cast<svt::BlockPartial *>(
         const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
     a.seq = (uint32_t)c->next_ticket;

@@ -7,7 +7,7 @@
 // Every word's place in the batch follows from counts over the words before
 // it, so the unpack is three data-parallel passes instead of a sequential
 // parse:
-//   tile_reduce  per tile of 4096 words: event headers, road headers, hits
+//   tile_reduce  per tile of 1024 words: event headers, road headers, hits
 //                declared by road headers, last road header, last event
 //                header (and a copy of the words into device memory when
 //                they are read from host-mapped memory);
@@ -23,7 +23,7 @@
 namespace svt {
 namespace {
 
-constexpr int kPer = 16;                       // words per thread
+constexpr int kPer = 4;                        // words per thread
 constexpr int kTile = kBlock * kPer;           // words per tile
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -57,8 +57,10 @@ __device__ __forceinline__ Agg agg_add(const Agg &x, const Agg &y)
                max(x.last_ev, y.last_ev)};
 }
 
-// Exclusive scan of one Agg per thread across the block (thread order), and
-// the block total.  Wavefront shuffles, then the wavefront totals in LDS.
+// Exclusive scan of one Agg per thread across a block of NT threads (thread
+// order), and the block total.  Wavefront shuffles, then the wavefront
+// totals in LDS.
+template <int NT>
 __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -78,7 +80,7 @@ __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
     Agg before{0, 0, 0, -1, -1};
     Agg tot{0, 0, 0, -1, -1};
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         if (w < wid) before = agg_add(before, s_w[w]);
         tot = agg_add(tot, s_w[w]);
     }
@@ -110,20 +112,22 @@ __global__ void __launch_bounds__(kBlock) tile_reduce(UnpackArgs a)
         }
     }
     Agg tot;
-    (void)block_excl(acc, s_w, tot);
+    (void)block_excl<kBlock>(acc, s_w, tot);
     if (threadIdx.x == 0) a.tiles[blockIdx.x] = tot;
 }
 
-// One block: tile prefixes, totals, the end-of-stream check, final offsets.
-__global__ void __launch_bounds__(kBlock) tile_scan(UnpackArgs a, int32_t n_tiles)
+// One block of kScan threads: tile prefixes, totals, the end-of-stream
+// check, final offsets.
+constexpr int kScan = 512;
+__global__ void __launch_bounds__(kScan) tile_scan(UnpackArgs a, int64_t n_tiles)
 {
-    __shared__ Agg s_w[kBlock / 64];
+    __shared__ Agg s_w[kScan / 64];
     Agg carry{0, 0, 0, -1, -1};
-    for (int32_t t0 = 0; t0 < n_tiles; t0 += kBlock) {
-        const int32_t t = t0 + (int32_t)threadIdx.x;
+    for (int64_t t0 = 0; t0 < n_tiles; t0 += kScan) {
+        const int64_t t = t0 + (int64_t)threadIdx.x;
         const Agg v = t < n_tiles ? a.tiles[t] : Agg{0, 0, 0, -1, -1};
         Agg tot;
-        const Agg ex = block_excl(v, s_w, tot);
+        const Agg ex = block_excl<kScan>(v, s_w, tot);
         if (t < n_tiles) a.tiles[t] = agg_add(carry, ex);
         carry = agg_add(carry, tot);
     }
@@ -145,11 +149,13 @@ __global__ void __launch_bounds__(kBlock) tile_scan(UnpackArgs a, int32_t n_tile
     }
 }
 
-__global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a)
+__global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_tiles)
 {
     __shared__ Agg s_w[kBlock / 64];
     __shared__ uint32_t s_bad[kBlock / 64];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
+    uint32_t bad = kNone;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t base = tile * kTile + (int64_t)threadIdx.x * kPer;
     uint32_t w[kPer];
     Agg acc{0, 0, 0, -1, -1};
 #pragma unroll
@@ -159,8 +165,10 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a)
         if (p < a.n_words) acc = agg_add(acc, agg_word(w[i], p));
     }
     Agg tot;
-    Agg pre = agg_add(a.tiles[blockIdx.x], block_excl(acc, s_w, tot));
-    uint32_t bad = kNone;
+    Agg pre = agg_add(a.tiles[tile], block_excl<kBlock>(acc, s_w, tot));
+    // the header of the last road before the thread's words (one load; the
+    // thread's own road headers replace it as they come)
+    uint32_t hdr = pre.last_road >= 0 ? a.words[pre.last_road] : 0u;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
         const int64_t p = base + i;
@@ -172,7 +180,7 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a)
         if (t == 3u || t == 2u) {
             // a header: the previous road of this event ends here, or the
             // event header that opens it is the word before
-            const int64_t expect = P > Q ? P + road_len(a.words[P]) : Q + 1;
+            const int64_t expect = P > Q ? P + road_len(hdr) : Q + 1;
             ok = (p == 0 && t == 3u) || (Q >= 0 && p == expect);
         }
         if (t == 3u) {
@@ -193,7 +201,6 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a)
             // XFT or hit word of the road whose header is at P
             ok = P > Q && (v & 0x3F000000u) == 0u;
             if (ok) {
-                const uint32_t hdr = a.words[P];
                 const int64_t r = pre.rd - 1;
                 if (t == 1u) {
                     ok = p == P + 1;
@@ -211,7 +218,9 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a)
             }
         }
         if (!ok) bad = min(bad, (uint32_t)p);
+        if (t == 2u) hdr = v;
         pre = agg_add(pre, agg_word(v, p));
+    }
     }
     // lowest flagged word of the block -> host-mapped partials
 #pragma unroll
@@ -231,14 +240,21 @@ int64_t unpack_tiles(int64_t n_words) { return (n_words + kTile - 1) / kTile; }
 
 size_t unpack_scratch_bytes(int64_t n_words) { return (size_t)(unpack_tiles(n_words) + 1) * sizeof(Agg); }
 
-int64_t unpack_max_words(int max_partials) { return (int64_t)(max_partials - 1) * kTile; }
+int64_t unpack_max_words() { return 0x7FFFFFFF; }   // word positions fit 31 bits
+
+int32_t unpack_apply_blocks(int64_t n_words, int max_partials)
+{
+    const int64_t t = unpack_tiles(n_words);
+    return (int32_t)(t < max_partials - 1 ? t : max_partials - 1);
+}
 
 hipError_t launch_unpack(UnpackArgs a, hipStream_t stream)
 {
     const int64_t tiles = unpack_tiles(a.n_words);
     if (tiles > 0) hipLaunchKernelGGL(tile_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
-    hipLaunchKernelGGL(tile_scan, dim3(1), dim3(kBlock), 0, stream, a, (int32_t)tiles);
-    if (tiles > 0) hipLaunchKernelGGL(tile_apply, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
+    hipLaunchKernelGGL(tile_scan, dim3(1), dim3(kScan), 0, stream, a, tiles);
+    if (tiles > 0 && a.n_apply > 0)
+        hipLaunchKernelGGL(tile_apply, dim3((unsigned)a.n_apply), dim3(kBlock), 0, stream, a, tiles);
     return hipGetLastError();
 }
 

@@ -91,7 +91,7 @@ def _corrupt(words, rng, how):
 
 @pytest.mark.parametrize("how", ["retag", "drop", "insert", "reserved", "truncate"])
 def test_first_bad_word_across_tiles(ctx, oracle_lib, how):
-    """Corruptions anywhere in a stream of many 4096-word tiles: the lowest
+    """Corruptions anywhere in a stream of many 1024-word tiles: the lowest
     flagged word equals the sequential parser's first failure."""
     from paper_1311_0380_amd import svt
     batch, _ = synth.cfg2(n_events=300)
@@ -162,5 +162,22 @@ def test_invalid_calls(ctx):
     bad = svt.svt_unpack_out(*[getattr(out, f).data_ptr() for f in FIELDS], -1, 4, 4, 0)
     st, _ = svt.svt_unpack_stream(ctx.handle, out.hits.data_ptr(), 0, 3, bad)
     assert st == svt.SVT_E_INVAL
-    st, _ = svt.svt_unpack_stream(ctx.handle, out.hits.data_ptr(), 1 << 40, 3, s)
+    st, _ = svt.svt_unpack_stream(ctx.handle, out.hits.data_ptr(), 1 << 31, 3, s)
     assert st == svt.SVT_E_INVAL
+
+
+def test_large_stream_grid_stride(ctx, oracle_lib):
+    """More tiles than the last pass has blocks (each block then loops over
+    several tiles): 10,000 events of 64 roads, 4.6 M words."""
+    batch, _ = synth.cfg2(n_events=10000)
+    words = synth.pack_stream(batch)
+    assert len(words) > 4096 * 1024
+    st, summ, got = ctx.unpack_stream(put(words, 3), mem_kind=3)
+    assert st == 0 and summ.total_comb == batch.n_roads
+    same_arrays(got, batch)
+    # and a bad word in the last tiles
+    w = words.copy()
+    w[len(w) - 100] |= np.uint32(1 << 29)
+    rc, _, _, bad = oracle_lib.unpack_stream(w)
+    st, summ, _ = ctx.unpack_stream(put(w, 3), mem_kind=3)
+    assert rc != 0 and summ.err_road == bad
