@@ -115,6 +115,7 @@ struct ListArgs {
     BlockPartial *partials;     // host-mapped, [gridDim.x]
     uint32_t seq;
 };
+constexpr int kListRoads = 64;   // roads per block of the list kernel
 hipError_t launch_list(const ListArgs &a, int grid, hipStream_t stream);
 
 // The unpack of a packed word stream (svt_unpack.hip).

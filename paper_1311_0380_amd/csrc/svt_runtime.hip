@@ -744,8 +744,8 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     a.partials = static_cast<svt::BlockPartial *>(
         const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
     a.seq = (uint32_t)c->next_ticket;
-    // one block per 256 roads, at most the partials' capacity
-    int64_t grid = ((int64_t)nr + svt::kBlock - 1) / svt::kBlock;
+    // one block per svt::kListRoads roads, at most the partials' capacity
+    int64_t grid = ((int64_t)nr + svt::kListRoads - 1) / svt::kListRoads;
     if (grid > c->max_grid) grid = c->max_grid;
     if (grid < 1) grid = 1;
 
