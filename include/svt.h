@@ -211,8 +211,9 @@ typedef struct {
  * place each road's entries, and roads with npass 0 are not evaluated again.
  * Events are not read.  svt_result() then gives total_pass = entries listed
  * (offsets[n_roads]) and total_comb = combinations evaluated; it returns
- * SVT_E_RANGE when a road is malformed or its passing combinations differ in
- * number from its npass (err_road = the lowest such road), or when the list
+ * SVT_E_RANGE when a road is malformed, its npass is negative or its passing
+ * combinations differ in number from its npass (err_road = the lowest such
+ * road), or when the list
  * exceeds capacity (err_road = -1; entries past capacity are not written).
  * Errors returned here: SVT_E_INVAL, SVT_E_STATE (no constants), SVT_E_AGAIN,
  * SVT_E_NOMEM, SVT_E_DEVICE.

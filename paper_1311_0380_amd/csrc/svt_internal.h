@@ -95,58 +95,6 @@ struct FitArgs {
     uint32_t seq;
 };
 
-// The list of every passing combination (svt_list.hip).
-struct ListArgs {
-    const uint8_t *sector;
-    const uint32_t *nhits4;
-    const int32_t *hit_offsets;
-    const int16_t *hits;
-    const uint32_t *xft2;
-    const int32_t *npass;       // pass counts of the fit, [n_roads]
-    const int64_t *offsets;     // exclusive running sum of npass, [n_roads + 1]
-    int32_t n_roads, n_hits, n_sectors;
-    const int32_t *coef;        // [n_sectors][6][6]
-    const int32_t *offset;      // [n_sectors][6]
-    uint64_t cut;
-    int32_t *k;                 // entries: combination index, chi2, fit rows 0..2
-    uint64_t *chi2;
-    int32_t *params;
-    int64_t capacity;
-    BlockPartial *partials;     // host-mapped, [gridDim.x]
-    uint32_t seq;
-};
-constexpr int kListRoads = 64;   // roads per block of the list kernel
-hipError_t launch_list(const ListArgs &a, int grid, hipStream_t stream);
-
-// The unpack of a packed word stream (svt_unpack.hip).
-struct UnpackAgg {              // over a range of words
-    int64_t ev, rd, hits;       // event headers, road headers, hits they declare
-    int64_t last_road, last_ev; // last road / event header, -1 if none
-};
-struct UnpackArgs {
-    const uint32_t *src;        // the words as given (device-visible)
-    uint32_t *words;            // the words in device memory (== src if already there)
-    int32_t copy;               // 1: the first pass copies src into words
-    int64_t n_words;
-    UnpackAgg *tiles;           // [tiles]: per tile, then the prefix before it
-    int32_t *road_offsets;      // outputs, [max_events + 1] ...
-    uint8_t *sector;
-    uint32_t *nhits4;
-    int32_t *hit_offsets;
-    int16_t *hits;
-    uint32_t *xft2;
-    int32_t max_events, max_roads, max_hits;
-    int32_t n_apply;            // blocks of the last pass (a grid-stride loop over the
-                                // tiles); the scan's partial follows theirs
-    BlockPartial *partials;     // host-mapped, [n_apply + 1]
-    uint32_t seq;
-};
-int64_t unpack_tiles(int64_t n_words);
-size_t unpack_scratch_bytes(int64_t n_words);
-int64_t unpack_max_words();
-int32_t unpack_apply_blocks(int64_t n_words, int max_partials);
-hipError_t launch_unpack(UnpackArgs a, hipStream_t stream);
-
 hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
 // start/stop non-NULL: the dispatch itself records them around the kernel
 // (no separate event packets on the stream).

@@ -14,6 +14,8 @@
 
 #include "svt.h"
 #include "svt_internal.h"
+#include "svt_list.h"
+#include "svt_unpack.h"
 #include "svt_shadow.h"
 
 namespace svt {
@@ -54,7 +56,7 @@ struct Slot {
     int grid = 0;                            // blocks of the request in flight
     svt_plan *plan = nullptr;                // plan of the request, if any
     DevBuf stage;                            // device staging for host inputs / results
-    DevBuf scan;                             // comb_offsets scratch
+    DevBuf scan;                             // scratch of the running sums (offsets scans)
     svt_status host_status = SVT_OK;
     int64_t list_capacity = -1;              // a passing-combination list: its capacity
     bool unpack = false;                     // a stream unpack: its capacities
@@ -719,7 +721,7 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     if (s.busy) return SVT_E_AGAIN;
     DeviceGuard g(c->device);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
-    svt_status r = ensure(c, s.scan, svt::comb_offsets_scratch_bytes(nr));
+    svt_status r = ensure(c, s.scan, svt::list_scratch_bytes(nr));
     if (r != SVT_OK) return r;
 
     svt::ListArgs a;
@@ -750,10 +752,7 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     if (grid < 1) grid = 1;
 
     HIP_TRY(hipEventRecord(s.ev_start, st));
-    hipError_t e = svt::launch_comb_offsets(npass, list->offsets, nr,
-                                            static_cast<int64_t *>(s.scan.ptr), st);
-    if (e != hipSuccess) return hip_fail(e, "pass offsets launch");
-    e = svt::launch_list(a, (int)grid, st);
+    hipError_t e = svt::launch_list(a, (int)grid, static_cast<int64_t *>(s.scan.ptr), st);
     if (e != hipSuccess) return hip_fail(e, "list kernel launch");
     HIP_TRY(hipEventRecord(s.ev_end, st));
     s.grid = (int)grid;

@@ -1,0 +1,37 @@
+// Declarations of the packed-word-stream unpack (svt_unpack.hip), shared
+// with the host runtime.
+#pragma once
+#include "svt_internal.h"
+
+namespace svt {
+
+// The unpack of a packed word stream (svt_unpack.hip).
+struct UnpackAgg {              // over a range of words
+    int64_t ev, rd, hits;       // event headers, road headers, hits they declare
+    int64_t last_road, last_ev; // last road / event header, -1 if none
+};
+struct UnpackArgs {
+    const uint32_t *src;        // the words as given (device-visible)
+    uint32_t *words;            // the words in device memory (== src if already there)
+    int32_t copy;               // 1: the first pass copies src into words
+    int64_t n_words;
+    UnpackAgg *tiles;           // [tiles]: per tile, then the prefix before it
+    int32_t *road_offsets;      // outputs, [max_events + 1] ...
+    uint8_t *sector;
+    uint32_t *nhits4;
+    int32_t *hit_offsets;
+    int16_t *hits;
+    uint32_t *xft2;
+    int32_t max_events, max_roads, max_hits;
+    int32_t n_apply;            // blocks of the last pass (a grid-stride loop over the
+                                // tiles); the scan's partial follows theirs
+    BlockPartial *partials;     // host-mapped, [n_apply + 1]
+    uint32_t seq;
+};
+int64_t unpack_tiles(int64_t n_words);
+size_t unpack_scratch_bytes(int64_t n_words);
+int64_t unpack_max_words();
+int32_t unpack_apply_blocks(int64_t n_words, int max_partials);
+hipError_t launch_unpack(UnpackArgs a, hipStream_t stream);
+
+}  // namespace svt

@@ -18,7 +18,7 @@
 //                parser would make at that word, and the writes.
 // The first word that breaks the format is the smallest flagged word: up to
 // it the stream is well formed, so every count there equals the parser's.
-#include "svt_internal.h"
+#include "svt_unpack.h"
 
 namespace svt {
 namespace {

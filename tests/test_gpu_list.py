@@ -118,6 +118,22 @@ def test_list_pass_count_mismatch(ctx):
     assert st == svt.SVT_E_RANGE and summ["err_road"] == bump.road
 
 
+def test_list_negative_npass(ctx):
+    """A negative pass count is reported as a bad road (the lowest one), ahead
+    of a later count mismatch."""
+    from paper_1311_0380_amd import svt
+    batch, consts = synth.cfg2(n_events=20)
+
+    def edit(npass):
+        nz = (npass > 0).nonzero().flatten()
+        npass[int(nz[3])] = -1
+        npass[int(nz[8])] += 1
+        edit.road = int(nz[3])
+
+    st, summ, _ = gpu_list(ctx, batch, consts, npass_edit=edit, capacity=1 << 20)
+    assert st == svt.SVT_E_RANGE and summ["err_road"] == edit.road
+
+
 def test_list_empty_and_no_pass(ctx, oracle_lib):
     from paper_1311_0380_amd import svt
     b0 = synth.Batch(road_offsets=np.zeros(1, np.int32), sector=np.zeros(0, np.uint8),
