@@ -833,6 +833,10 @@ svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words,
     } else if (!in_device && n_words > 0) {
         HIP_TRY(hipMemcpyAsync(dev_words, words, 4 * (size_t)n_words, hipMemcpyHostToDevice, st));
     }
+    // host-mapped words are read four bytes per lane: 16-byte reads over
+    // the bus were slower
+    a.src_vec = a.copy == 0 && (reinterpret_cast<uintptr_t>(a.src) & 15u) == 0;
+    a.words_vec = (reinterpret_cast<uintptr_t>(a.words) & 15u) == 0;
     hipError_t e = svt::launch_unpack(a, st);
     if (e != hipSuccess) return hip_fail(e, "unpack launch");
     HIP_TRY(hipEventRecord(s.ev_end, st));

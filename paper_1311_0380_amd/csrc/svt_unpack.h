@@ -6,14 +6,16 @@
 namespace svt {
 
 // The unpack of a packed word stream (svt_unpack.hip).
-struct UnpackAgg {              // over a range of words
-    int64_t ev, rd, hits;       // event headers, road headers, hits they declare
-    int64_t last_road, last_ev; // last road / event header, -1 if none
+struct UnpackAgg {              // over a range of words (positions < 2^31)
+    int64_t hits;               // hits the road headers declare
+    int32_t ev, rd;             // event headers, road headers
+    int32_t last_road, last_ev; // last road / event header, -1 if none
 };
 struct UnpackArgs {
     const uint32_t *src;        // the words as given (device-visible)
     uint32_t *words;            // the words in device memory (== src if already there)
     int32_t copy;               // 1: the first pass copies src into words
+    int32_t src_vec, words_vec; // 1: src / words 16-byte aligned (4-word loads)
     int64_t n_words;
     UnpackAgg *tiles;           // [tiles]: per tile, then the prefix before it
     int32_t *road_offsets;      // outputs, [max_events + 1] ...

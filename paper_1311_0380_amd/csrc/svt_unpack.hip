@@ -37,9 +37,11 @@ __device__ __forceinline__ uint32_t road_hits(uint32_t w)
     return (c & 31u) + ((c >> 5) & 31u) + ((c >> 10) & 31u) + ((c >> 15) & 31u);
 }
 // words of a road: header, XFT word, ceil(hits / 2) hit words
-__device__ __forceinline__ int64_t road_len(uint32_t header) { return 2 + (road_hits(header) + 1) / 2; }
+__device__ __forceinline__ int32_t road_len(uint32_t header) { return 2 + (int32_t)(road_hits(header) + 1) / 2; }
 
-__device__ __forceinline__ Agg agg_word(uint32_t w, int64_t pos)
+constexpr Agg kZero{0, 0, 0, -1, -1};
+
+__device__ __forceinline__ Agg agg_word(uint32_t w, int32_t pos)
 {
     const uint32_t t = tag_of(w);
     Agg a;
@@ -53,9 +55,37 @@ __device__ __forceinline__ Agg agg_word(uint32_t w, int64_t pos)
 
 __device__ __forceinline__ Agg agg_add(const Agg &x, const Agg &y)
 {
-    return Agg{x.ev + y.ev, x.rd + y.rd, x.hits + y.hits, max(x.last_road, y.last_road),
+    return Agg{x.hits + y.hits, x.ev + y.ev, x.rd + y.rd, max(x.last_road, y.last_road),
                max(x.last_ev, y.last_ev)};
 }
+
+__device__ __forceinline__ Agg shfl_up(const Agg &v, int off)
+{
+    Agg o;
+    o.hits = __shfl_up(v.hits, off, 64);
+    o.ev = __shfl_up(v.ev, off, 64);
+    o.rd = __shfl_up(v.rd, off, 64);
+    o.last_road = __shfl_up(v.last_road, off, 64);
+    o.last_ev = __shfl_up(v.last_ev, off, 64);
+    return o;
+}
+
+// the kPer words of a thread: one 16-byte load when aligned and whole
+__device__ __forceinline__ void load_words(const uint32_t *src, int64_t base, int64_t n, bool vec,
+                                           uint32_t (&w)[kPer])
+{
+    if (vec && base + kPer <= n) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(src + base);
+        w[0] = q.x;
+        w[1] = q.y;
+        w[2] = q.z;
+        w[3] = q.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) w[i] = base + i < n ? src[base + i] : 0u;
+    }
+}
+static_assert(kPer == 4, "one 16-byte load per thread");
 
 // Exclusive scan of one Agg per thread across a block of NT threads (thread
 // order), and the block total.  Wavefront shuffles, then the wavefront
@@ -67,18 +97,12 @@ __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
     Agg incl = v;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        Agg o;
-        o.ev = __shfl_up(incl.ev, off, 64);
-        o.rd = __shfl_up(incl.rd, off, 64);
-        o.hits = __shfl_up(incl.hits, off, 64);
-        o.last_road = __shfl_up(incl.last_road, off, 64);
-        o.last_ev = __shfl_up(incl.last_ev, off, 64);
+        const Agg o = shfl_up(incl, off);
         if (lane >= off) incl = agg_add(o, incl);
     }
     if (lane == 63) s_w[wid] = incl;
     __syncthreads();
-    Agg before{0, 0, 0, -1, -1};
-    Agg tot{0, 0, 0, -1, -1};
+    Agg before = kZero, tot = kZero;
 #pragma unroll
     for (int w = 0; w < NT / 64; ++w) {
         if (w < wid) before = agg_add(before, s_w[w]);
@@ -87,13 +111,8 @@ __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
     __syncthreads();
     total = tot;
     // exclusive = before + (inclusive of this lane's predecessors)
-    Agg prev;
-    prev.ev = __shfl_up(incl.ev, 1, 64);
-    prev.rd = __shfl_up(incl.rd, 1, 64);
-    prev.hits = __shfl_up(incl.hits, 1, 64);
-    prev.last_road = __shfl_up(incl.last_road, 1, 64);
-    prev.last_ev = __shfl_up(incl.last_ev, 1, 64);
-    if (lane == 0) prev = Agg{0, 0, 0, -1, -1};
+    Agg prev = shfl_up(incl, 1);
+    if (lane == 0) prev = kZero;
     return agg_add(before, prev);
 }
 
@@ -101,34 +120,50 @@ __global__ void __launch_bounds__(kBlock) tile_reduce(UnpackArgs a)
 {
     __shared__ Agg s_w[kBlock / 64];
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kPer;
-    Agg acc{0, 0, 0, -1, -1};
+    uint32_t w[kPer];
+    load_words(a.src, base, a.n_words, a.src_vec != 0, w);
+    if (a.copy) {
+        if (a.words_vec && base + kPer <= a.n_words) {
+            *reinterpret_cast<uint4 *>(a.words + base) = make_uint4(w[0], w[1], w[2], w[3]);
+        } else {
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const int64_t p = base + i;
-        if (p < a.n_words) {
-            const uint32_t w = a.src[p];
-            if (a.copy) a.words[p] = w;
-            acc = agg_add(acc, agg_word(w, p));
+            for (int i = 0; i < kPer; ++i)
+                if (base + i < a.n_words) a.words[base + i] = w[i];
         }
     }
+    Agg acc = kZero;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+        if (base + i < a.n_words) acc = agg_add(acc, agg_word(w[i], (int32_t)(base + i)));
     Agg tot;
     (void)block_excl<kBlock>(acc, s_w, tot);
     if (threadIdx.x == 0) a.tiles[blockIdx.x] = tot;
 }
 
-// One block of kScan threads: tile prefixes, totals, the end-of-stream
+// One block of kScan threads: tile prefixes (kSeq consecutive tiles per
+// thread, one block scan per kScan * kSeq tiles), totals, the end-of-stream
 // check, final offsets.
 constexpr int kScan = 512;
+constexpr int kSeq = 4;
 __global__ void __launch_bounds__(kScan) tile_scan(UnpackArgs a, int64_t n_tiles)
 {
     __shared__ Agg s_w[kScan / 64];
-    Agg carry{0, 0, 0, -1, -1};
-    for (int64_t t0 = 0; t0 < n_tiles; t0 += kScan) {
-        const int64_t t = t0 + (int64_t)threadIdx.x;
-        const Agg v = t < n_tiles ? a.tiles[t] : Agg{0, 0, 0, -1, -1};
+    Agg carry = kZero;
+    for (int64_t t0 = 0; t0 < n_tiles; t0 += kScan * kSeq) {
+        const int64_t t = t0 + (int64_t)threadIdx.x * kSeq;
+        Agg v[kSeq];
+#pragma unroll
+        for (int i = 0; i < kSeq; ++i) v[i] = t + i < n_tiles ? a.tiles[t + i] : kZero;
+        Agg sum = v[0];
+#pragma unroll
+        for (int i = 1; i < kSeq; ++i) sum = agg_add(sum, v[i]);
         Agg tot;
-        const Agg ex = block_excl<kScan>(v, s_w, tot);
-        if (t < n_tiles) a.tiles[t] = agg_add(carry, ex);
+        Agg ex = agg_add(carry, block_excl<kScan>(sum, s_w, tot));
+#pragma unroll
+        for (int i = 0; i < kSeq; ++i) {
+            if (t + i < n_tiles) a.tiles[t + i] = ex;
+            ex = agg_add(ex, v[i]);
+        }
         carry = agg_add(carry, tot);
     }
     if (threadIdx.x == 0) {
@@ -138,8 +173,8 @@ __global__ void __launch_bounds__(kScan) tile_scan(UnpackArgs a, int64_t n_tiles
         const int64_t W = a.n_words;
         if (W > 0) {
             const int64_t end = carry.last_road > carry.last_ev
-                                    ? carry.last_road + road_len(a.words[carry.last_road])
-                                    : carry.last_ev + 1;
+                                    ? (int64_t)carry.last_road + road_len(a.words[carry.last_road])
+                                    : (int64_t)carry.last_ev + 1;
             if (end != W) bad = (uint32_t)W;
         }
         if (carry.ev <= a.max_events) a.road_offsets[carry.ev] = (int32_t)carry.rd;
@@ -157,13 +192,11 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_til
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t base = tile * kTile + (int64_t)threadIdx.x * kPer;
     uint32_t w[kPer];
-    Agg acc{0, 0, 0, -1, -1};
+    load_words(a.words, base, a.n_words, a.words_vec != 0, w);
+    Agg acc = kZero;
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const int64_t p = base + i;
-        w[i] = p < a.n_words ? a.words[p] : 0u;
-        if (p < a.n_words) acc = agg_add(acc, agg_word(w[i], p));
-    }
+    for (int i = 0; i < kPer; ++i)
+        if (base + i < a.n_words) acc = agg_add(acc, agg_word(w[i], (int32_t)(base + i)));
     Agg tot;
     Agg pre = agg_add(a.tiles[tile], block_excl<kBlock>(acc, s_w, tot));
     // the header of the last road before the thread's words (one load; the
@@ -175,12 +208,12 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_til
         if (p >= a.n_words) break;
         const uint32_t v = w[i], t = tag_of(v);
         // pre holds the counts over the words before p
-        const int64_t P = pre.last_road, Q = pre.last_ev;
+        const int32_t P = pre.last_road, Q = pre.last_ev;
         bool ok = true;
         if (t == 3u || t == 2u) {
             // a header: the previous road of this event ends here, or the
             // event header that opens it is the word before
-            const int64_t expect = P > Q ? P + road_len(hdr) : Q + 1;
+            const int64_t expect = P > Q ? (int64_t)P + road_len(hdr) : (int64_t)Q + 1;
             ok = (p == 0 && t == 3u) || (Q >= 0 && p == expect);
         }
         if (t == 3u) {
@@ -208,7 +241,7 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_til
                 } else {
                     const int64_t S = road_hits(hdr);
                     const int64_t j = 2 * (p - P - 2);
-                    ok = p >= P + 2 && p < P + road_len(hdr) && (j + 1 < S || (v & 0xFFF000u) == 0u);
+                    ok = p >= P + 2 && p < (int64_t)P + road_len(hdr) && (j + 1 < S || (v & 0xFFF000u) == 0u);
                     if (ok) {
                         const int64_t h = pre.hits - S + j;   // pre.hits counts this road's hits
                         if (h < a.max_hits) a.hits[h] = (int16_t)(v & 0xFFFu);
@@ -219,7 +252,7 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_til
         }
         if (!ok) bad = min(bad, (uint32_t)p);
         if (t == 2u) hdr = v;
-        pre = agg_add(pre, agg_word(v, p));
+        pre = agg_add(pre, agg_word(v, (int32_t)p));
     }
     }
     // lowest flagged word of the block -> host-mapped partials

@@ -110,6 +110,22 @@ def test_first_bad_word_across_tiles(ctx, oracle_lib, how):
     assert seen > 0
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_unaligned_device_words(ctx, shift):
+    """Words at an address that is not 16-byte aligned (4-byte loads instead
+    of 16-byte ones), with a ragged tail."""
+    import torch
+    batch, _ = synth.cfg2(n_events=50)
+    words = synth.pack_stream(batch)
+    buf = torch.zeros(len(words) + 4, dtype=torch.int32, device="cuda")
+    buf[shift:shift + len(words)] = torch.from_numpy(words.view(np.int32)).cuda()
+    view = buf[shift:shift + len(words)]
+    assert view.data_ptr() % 16 != 0
+    st, summ, got = ctx.unpack_stream(view, mem_kind=3)
+    assert st == 0, summ.as_dict()
+    same_arrays(got, batch, f"shift {shift}: ")
+
+
 def test_capacity(ctx, oracle_lib):
     from paper_1311_0380_amd import svt
     batch, _ = synth.cfg2(n_events=30)
