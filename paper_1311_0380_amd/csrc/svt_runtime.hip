@@ -59,6 +59,7 @@ struct Slot {
     DevBuf scan;                             // scratch of the running sums (offsets scans)
     svt_status host_status = SVT_OK;
     int64_t list_capacity = -1;              // a passing-combination list: its capacity
+    bool timed = true;                       // ev_start was recorded (device_ns valid)
     bool unpack = false;                     // a stream unpack: its capacities
     int64_t unpack_cap[3] = {0, 0, 0};
 };
@@ -90,6 +91,7 @@ struct svt_ctx {
     std::vector<DevBuf> pool;                // idle staging buffers
     uint64_t const_gen = 0;                  // bumped by every svt_load_constants
     svt_tuning tuning{0, 0, 1, 0};  // automatic chunk, occupancy and kernel; cyclic
+    int32_t timing_every = 1;                // fit requests that record their start
 };
 
 // A captured fit of any batch up to a fixed capacity (see svt_plan_create).
@@ -513,6 +515,13 @@ svt_status svt_set_tuning(svt_ctx *c, const svt_tuning *t)
     return SVT_OK;
 }
 
+svt_status svt_set_timing(svt_ctx *c, int32_t every)
+{
+    if (c == nullptr || every < 0) return SVT_E_INVAL;
+    c->timing_every = every;
+    return SVT_OK;
+}
+
 svt_status svt_get_tuning(svt_ctx *c, svt_tuning *t)
 {
     if (c == nullptr || t == nullptr) return SVT_E_INVAL;
@@ -614,7 +623,9 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     // packets of its own on the stream); copies or the offsets scan need
     // events around the whole request
     const bool kernel_only = !stage_in && !stage_out && res->comb_offsets == nullptr;
-    if (!kernel_only) HIP_TRY(hipEventRecord(s.ev_start, st));
+    const int32_t every = c->timing_every;
+    const bool timed = every == 1 || (every > 1 && c->next_ticket % every == 0);
+    if (!kernel_only && timed) HIP_TRY(hipEventRecord(s.ev_start, st));
     if (stage_in) {
         const hipMemcpyKind k = hipMemcpyHostToDevice;
         HIP_TRY(hipMemcpyAsync(base + o_ro, b->road_offsets, b_ro, k, st));
@@ -671,7 +682,9 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     s.parts = s.partials;
     s.plan = nullptr;
 
-    hipError_t e = kernel_only ? launch_shaped(c, a, ls, st, s.ev_start, s.ev_end)
+    // a kernel-only request: the dispatch itself records the events (only
+    // the completion when untimed)
+    hipError_t e = kernel_only ? launch_shaped(c, a, ls, st, timed ? s.ev_start : nullptr, s.ev_end)
                                : launch_shaped(c, a, ls, st);
     if (e != hipSuccess) return hip_fail(e, "fit kernel launch");
     if (co_dev) {
@@ -693,6 +706,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     }
     if (!kernel_only) HIP_TRY(hipEventRecord(s.ev_end, st));
     guard.keep = true;
+    s.timed = timed;
     s.busy = true;
     s.ticket = c->next_ticket++;
     *ticket = s.ticket;
@@ -909,7 +923,9 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
         out->err_event = ee == 0xFFFFFFFFu ? -1 : (int32_t)ee;
         out->status = status;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, s.ev_start, s.ev_end) == hipSuccess)
+        if (!s.timed)
+            out->device_ns = 0;
+        else if (hipEventElapsedTime(&ms, s.ev_start, s.ev_end) == hipSuccess)
             out->device_ns = (int64_t)((double)ms * 1e6);
         else
             (void)hipGetLastError();
@@ -919,6 +935,7 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     stage_release(c, s.stage);
     s.list_capacity = -1;
     s.unpack = false;
+    s.timed = true;
     s.busy = false;
     s.ticket = -1;
     return status;

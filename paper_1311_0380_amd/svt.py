@@ -93,6 +93,7 @@ SIGNATURES = {
     "svt_last_error": (ctypes.c_char_p, []),
     "svt_set_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
     "svt_get_tuning": (ctypes.c_int32, [P, ctypes.POINTER(svt_tuning)]),
+    "svt_set_timing": (ctypes.c_int32, [P, ctypes.c_int32]),
     "svt_get_device_info": (ctypes.c_int32, [P, ctypes.POINTER(svt_device_info)]),
     "svt_io_probe": (ctypes.c_int32, [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t,
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
@@ -190,6 +191,10 @@ def svt_status_string(status: int) -> str:
 def svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=0, schedule=0, kernel=0):
     t = svt_tuning(int(events_per_chunk), int(blocks_per_cu), int(schedule), int(kernel))
     return lib.svt_set_tuning(ctx, ctypes.byref(t))
+
+
+def svt_set_timing(ctx, every: int):
+    return lib.svt_set_timing(ctx, int(every))
 
 
 def svt_get_tuning(ctx) -> dict:
@@ -462,6 +467,11 @@ class Context:
 
     def tuning(self):
         return svt_get_tuning(self.handle)
+
+    def set_timing(self, every: int):
+        """Which later fit requests measure their device time (1 all, N every
+        N-th ticket, 0 none); untimed ones report device_ns 0."""
+        check(svt_set_timing(self.handle, every), "svt_set_timing")
 
     def device_info(self):
         return svt_get_device_info(self.handle)

@@ -88,6 +88,18 @@ def test_list_full_scaled_up_batch(ctx, oracle_lib):
     assert_same_list(got, want, "3000 events: ")
 
 
+def test_list_grid_stride(ctx, oracle_lib):
+    """More roads than the grid covers in one pass (1,056,000 roads: blocks of
+    the list kernel loop over groups, the tile sums over tiles), every entry."""
+    batch, consts = synth.cfg2(n_events=16500)
+    assert batch.n_roads > 4096 * 256
+    rc, want, _ = oracle_lib.list_passing_batch(batch, consts)
+    assert rc == 0
+    st, summ, got = gpu_list(ctx, batch, consts)
+    assert st == 0, summ
+    assert_same_list(got, want, "16500 events: ")
+
+
 def test_list_capacity(ctx, oracle_lib):
     """A list that does not fit: SVT_E_RANGE with err_road -1, complete
     offsets, and the entries that fit equal the start of the full list."""

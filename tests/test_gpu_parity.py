@@ -211,6 +211,32 @@ def test_repeatable_bits(ctx):
     assert s1["total_pass"] == s2["total_pass"]
 
 
+@pytest.mark.parametrize("kinds", [(3, 3), (1, 1)])
+def test_sampled_timing(ctx, kinds):
+    """svt_set_timing: untimed requests (only their completion recorded)
+    report device_ns 0 and the same bits, timed ones a device time; a
+    negative setting is refused."""
+    from paper_1311_0380_amd import svt
+    batch, consts = synth.cfg2(n_events=64)
+    load(ctx, consts)
+    _, s0, want = lib_fit(ctx, batch, *kinds)
+    assert s0["device_ns"] > 0
+    try:
+        for every in (3, 0):
+            svt.check(svt.svt_set_timing(ctx, every))
+            seen = set()
+            for _ in range(6):
+                st, s, got = lib_fit(ctx, batch, *kinds)
+                assert st == 0
+                assert_equal_results(got, want)
+                assert s["total_pass"] == s0["total_pass"]
+                seen.add(s["device_ns"] > 0)
+            assert seen == ({True, False} if every == 3 else {False})
+        assert svt.svt_set_timing(ctx, -1) == svt.SVT_E_INVAL
+    finally:
+        svt.check(svt.svt_set_timing(ctx, 1))
+
+
 # ---------------------------------------------------------------------------
 # malformed data: same status and offending road / event as the oracle
 # ---------------------------------------------------------------------------
