@@ -273,23 +273,27 @@ def section_uneven(args, svt, synth, torch, uneven):
     inb, outb = plan.inb, plan.outb
     plan.fit(b, r)                       # inputs now in the plan's buffers
     inb.n_events, inb.n_roads, inb.n_hits = batch.n_events, batch.n_roads, batch.n_hits
+    # wall times with no request timed (neither form needs device times
+    # there); device times in runs of their own
+    ctx.set_timing(0)
     lat = []
     for _ in range(args.uneven_reps):
         t0 = time.perf_counter()
         st, s = plan.fit(inb, outb)
         lat.append(time.perf_counter() - t0)
         svt.check(st)
+    per = uneven.PerEventBatches(batch)
+    per.run(ctx)                         # warm
+    plain_wall = []
+    for _ in range(3):
+        w, _, _ = per.run(ctx)
+        plain_wall.append(w)
+    ctx.set_timing(1)
     dev = []
     for _ in range(args.uneven_reps):
         st, s = plan.fit(inb, outb)
         dev.append(s.device_ns)
-    per = uneven.PerEventBatches(batch)
-    per.run(ctx)                         # warm
-    plain_wall, plain_dev = [], None
-    for _ in range(3):
-        w, dns, _ = per.run(ctx)
-        plain_wall.append(w)
-        plain_dev = dns
+    _, plain_dev, _ = per.run(ctx)
     plan.close()
     ctx.close()
     total = int(np.prod(batch.nhits.astype(np.int64), axis=1).sum())

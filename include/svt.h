@@ -272,7 +272,8 @@ const char *svt_last_error(void);
 svt_status svt_set_tuning(svt_ctx *ctx, const svt_tuning *tuning);
 svt_status svt_get_tuning(svt_ctx *ctx, svt_tuning *tuning);
 
-/* Which later svt_fit_events requests measure their device time: every = 1
+/* Which later fit requests (svt_fit_events, svt_plan_fit) measure their
+ * device time: every = 1
  * (the default) all of them, every = N > 1 those whose ticket is a multiple
  * of N, every = 0 none.  An untimed request records only its completion on
  * the stream, which costs the host far less per launch than a start

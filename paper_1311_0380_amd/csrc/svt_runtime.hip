@@ -1217,7 +1217,9 @@ svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results
         if (r != SVT_OK) return r;
     }
 
-    HIP_TRY(hipEventRecord(s.ev_start, st));
+    const int32_t every = c->timing_every;
+    const bool timed = every == 1 || (every > 1 && c->next_ticket % every == 0);
+    if (timed) HIP_TRY(hipEventRecord(s.ev_start, st));
     // inputs into the plan's buffers (skipped when the caller filled them in place)
     const void *src[6] = {b->road_offsets, b->sector, b->nhits, b->hit_offsets, b->hits, b->xft};
     const void *dst[6] = {p->in.road_offsets, p->in.sector, p->in.nhits, p->in.hit_offsets,
@@ -1247,6 +1249,7 @@ svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results
     for (int i = 0; i < 7; ++i)
         if (rb[i] && rd[i] != rs[i]) HIP_TRY(hipMemcpyAsync(rd[i], rs[i], rb[i], hipMemcpyDefault, st));
     HIP_TRY(hipEventRecord(s.ev_end, st));
+    s.timed = timed;
     s.busy = true;
     s.ticket = c->next_ticket++;
     s.parts = p->partials;

@@ -73,6 +73,28 @@ def test_plan_in_place_buffers(env, oracle_lib):
         plan.close()
 
 
+def test_plan_untimed_replays(env, oracle_lib):
+    """Plan replays that svt_set_timing leaves untimed report device_ns 0
+    and the same bits; timed ones a device time."""
+    uneven = env["uneven"]
+    ctx = env["ctx"]
+    sub = env["batch"].select_events(0, 1500)
+    rc, want, _ = oracle_lib.fit_batch(sub, env["consts"], n_threads=8)
+    assert rc == 0
+    plan = uneven.Plan(ctx, sub.n_events, sub.n_roads, sub.n_hits)
+    try:
+        for every, timed in ((0, False), (1, True)):
+            ctx.set_timing(every)
+            for _ in range(2):
+                st, summ, got = plan_fit(env, plan, sub)
+                assert st == 0
+                assert_equal_results(got, want, where=f"timing {every}: ")
+                assert (summ.device_ns > 0) == timed
+    finally:
+        ctx.set_timing(1)
+        plan.close()
+
+
 def test_plan_errors(env):
     svt, uneven = env["svt"], env["uneven"]
     batch, consts = env["batch"], env["consts"]
