@@ -116,6 +116,28 @@ __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
     return agg_add(before, prev);
 }
 
+// Sum of one Agg per thread across the block (wavefront butterflies, then
+// the wavefront sums in LDS); the same in every thread.
+__device__ Agg block_total(Agg v, Agg *s_w)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        Agg o;
+        o.hits = __shfl_xor(v.hits, off, 64);
+        o.ev = __shfl_xor(v.ev, off, 64);
+        o.rd = __shfl_xor(v.rd, off, 64);
+        o.last_road = __shfl_xor(v.last_road, off, 64);
+        o.last_ev = __shfl_xor(v.last_ev, off, 64);
+        v = agg_add(v, o);
+    }
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    Agg tot = kZero;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) tot = agg_add(tot, s_w[w]);
+    return tot;
+}
+
 __global__ void __launch_bounds__(kBlock) tile_reduce(UnpackArgs a)
 {
     __shared__ Agg s_w[kBlock / 64];
@@ -135,8 +157,7 @@ __global__ void __launch_bounds__(kBlock) tile_reduce(UnpackArgs a)
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
         if (base + i < a.n_words) acc = agg_add(acc, agg_word(w[i], (int32_t)(base + i)));
-    Agg tot;
-    (void)block_excl<kBlock>(acc, s_w, tot);
+    const Agg tot = block_total(acc, s_w);
     if (threadIdx.x == 0) a.tiles[blockIdx.x] = tot;
 }
 
@@ -193,12 +214,13 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_til
     const int64_t base = tile * kTile + (int64_t)threadIdx.x * kPer;
     uint32_t w[kPer];
     load_words(a.words, base, a.n_words, a.words_vec != 0, w);
+    const Agg tile_pre = a.tiles[tile];   // in flight with the words
     Agg acc = kZero;
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
         if (base + i < a.n_words) acc = agg_add(acc, agg_word(w[i], (int32_t)(base + i)));
     Agg tot;
-    Agg pre = agg_add(a.tiles[tile], block_excl<kBlock>(acc, s_w, tot));
+    Agg pre = agg_add(tile_pre, block_excl<kBlock>(acc, s_w, tot));
     // the header of the last road before the thread's words (one load; the
     // thread's own road headers replace it as they come)
     uint32_t hdr = pre.last_road >= 0 ? a.words[pre.last_road] : 0u;
