@@ -100,17 +100,24 @@ def section_fit(args, svt, synth, torch):
     bs = [c.struct() for c in copies]
     rs = [r.struct() for r in results]
     stream = torch.cuda.current_stream().cuda_stream
-    # dispatch events on one request in time_every: a start timestamp costs
-    # the host about 11 us per launch, the completion alone about 3 us
     if args.time_every < 1:
         raise SystemExit("--time-every must be at least 1 (the roofline needs timed launches)")
+    if args.fit_streams < 1 or args.copies % args.fit_streams:
+        # request i reuses the buffers of request i - copies: same stream, so in order
+        raise SystemExit("--fit-streams must be at least 1 and divide --copies")
+    # requests alternate over independent streams (default priority), so that
+    # one launch's tail and set-up overlap the next one's row loops
+    streams = [torch.cuda.Stream() for _ in range(args.fit_streams)]
+    handles = [s.cuda_stream for s in streams]
+    # dispatch events on one request in time_every: a start timestamp costs
+    # the host about 11 us per launch, the completion alone about 3 us
     ctx.set_timing(args.time_every)
     torch.cuda.synchronize()
 
     def run(n):
         pend, dev_ns, total = [], [], 0
         for i in range(n):
-            pend.append(ctx.submit(bs[i % args.copies], rs[i % args.copies], stream))
+            pend.append(ctx.submit(bs[i % args.copies], rs[i % args.copies], handles[i % len(handles)]))
             if len(pend) > 32:
                 st, s = ctx.result(pend.pop(0), -1)
                 svt.check(st, "fit")
@@ -140,6 +147,7 @@ def section_fit(args, svt, synth, torch):
     kernel_s = float(np.mean(timed)) * 1e-9
     alg = algorithmic_bytes(batch.n_events, batch.n_roads, batch.n_hits)
     achieved = alg / kernel_s / 1e9
+    effective = alg * args.steps / elapsed / 1e9   # launches overlap: bytes per wall second
     out = dict(
         value=total / elapsed, ms_per_step=elapsed * 1e3 / args.steps,
         combinations=int(total // args.steps),
@@ -148,11 +156,12 @@ def section_fit(args, svt, synth, torch):
                 "n_events": batch.n_events, "n_roads": batch.n_roads, "n_hits": batch.n_hits,
                 "combinations": int(total // args.steps), "chi2_cut": consts.chi2_cut,
                 "device": info["arch"], "compute_units": info["compute_units"],
-                "tuning": ctx.tuning(), "input_copies": args.copies},
+                "tuning": ctx.tuning(), "input_copies": args.copies, "streams": args.fit_streams},
         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                   "kernel_us": kernel_s * 1e6, "algorithmic_bytes": alg,
                   "timed_launches": len(timed),
+                  "effective_gbs": effective, "effective_frac": effective / HBM_PEAK_GBS,
                   "isolated_request_us_p50": pct(iso, 50) / 1e3},
         batch=batch, consts=consts)
     ctx.close()
@@ -444,6 +453,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--copies", type=int, default=32)
+    ap.add_argument("--fit-streams", type=int, default=2,
+                    help="streams the fit requests of the timed region alternate over")
     ap.add_argument("--time-every", type=int, default=8,
                     help="fit requests of the timed region that carry dispatch events: one in N")
     ap.add_argument("--sections", default="fit,list,unpack,uneven,serve,io,shadow")
