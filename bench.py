@@ -102,8 +102,9 @@ def section_fit(args, svt, synth, torch):
     bs = [c.struct() for c in copies]
     rs = [r.struct() for r in results]
     stream = torch.cuda.current_stream().cuda_stream
-    if args.time_every < 1:
-        raise SystemExit("--time-every must be at least 1 (the roofline needs timed launches)")
+    if args.time_every < 1 or args.steps < args.time_every:
+        raise SystemExit("--time-every must be at least 1 and at most --steps "
+                         "(the roofline needs timed launches)")
     if args.fit_streams < 1 or args.copies % args.fit_streams:
         # request i reuses the buffers of request i - copies: same stream, so in order
         raise SystemExit("--fit-streams must be at least 1 and divide --copies")
