@@ -73,7 +73,7 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
 
-def cpu_baseline(batch, consts, min_seconds=10.0, max_reps=200):
+def cpu_baseline(batch, consts, min_seconds=10.0, max_reps=5000):
     import oracle
     oracle.build(force=False)
     threads = max(1, min(16, os.cpu_count() or 1))
