@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
             h1 = a.hit_offsets[r + 1];
             x2 = a.xft2[r];
         }
-        // npass of the tile's roads before this group (at most 3 per lane)
+        // npass of the tile's roads before this group (at most four loads per lane)
         const int32_t ts = r0 - r0 % kListTile;
         int64_t before = 0;
 #pragma unroll
@@ -242,7 +242,7 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
             }
             int32_t z[6];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) z[k] = b[k] + A[k][4] * xa + A[k][5] * xb;
+            for (int k = 0; k < 6; ++k) z[k] = b[k] + __mul24(A[k][4], xa) + __mul24(A[k][5], xb);
             RoadRec &q = rec[lane];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
