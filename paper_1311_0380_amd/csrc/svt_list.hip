@@ -15,8 +15,9 @@
 //   with the XFT columns folded into each row's constant part, the hit counts
 //   and the constants of the division by them, and its first slot in the
 //   wavefront's run of combinations, which puts those roads' combinations one
-//   after the other in road order and index order; its hits are staged in
-//   LDS beside the records.  The wavefront then walks the run 64 slots per
+//   after the other in road order and index order; the group's hits are
+//   staged in LDS beside the records (the group's hit range at once, or road
+//   by road when a road's hits lie outside it).  The wavefront then walks the run 64 slots per
 //   round, whatever roads they belong to: each lane finds its road by a
 //   binary search over the roads' first slots, decodes its combination index
 //   k into (i0, i1, i2, i3) by multiply-high division, and evaluates the
@@ -42,7 +43,7 @@ static_assert(kListTile % kRoadsPerWave == 0 && kListTile <= 4 * 64, "tile of th
 // One road of a wavefront, as its lanes read it.
 struct alignas(16) RoadRec {
     int4 chi[3];   // constraint rows 3..5, hit columns 0..3
-    int4 zc;       // constant parts of rows 3..5, hit counts (4 x 8 bits)
+    int4 zc;       // constant parts of rows 3..5; hit counts (4 x 5 bits) | first hit in LDS << 20
     int4 dec;      // first slot, division constants of n1, n2, n3
     int4 pos;      // passing slots before the first slot, npass, list offset (low, high)
     int4 par[3];   // parameter rows 0..2, hit columns 0..3
@@ -203,8 +204,32 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
         const uint32_t start = lane < (uint32_t)kRoadsPerWave ? incl - nc : total;
         if (lane < (uint32_t)kRoadsPerWave) first[lane] = start;
 
-        // the group's hits, road by road (lanes take a road's hits at once)
-        {
+        // the group's hits in LDS: its hit range when every road to evaluate
+        // lies inside it (then a road's hits start at h0 - hs), else road by
+        // road at 64 places each
+        const int32_t hs = __builtin_amdgcn_readfirstlane(h0);
+        const int32_t he = __builtin_amdgcn_readlane(h1, r1 - r0 - 1);
+        const bool range = hs >= 0 && hs <= he && he <= a.n_hits &&
+                           he - hs <= kRoadsPerWave * kRoadHitCap &&
+                           __ballot(walk && (h0 < hs || h1 > he)) == 0;
+        uint32_t hbase;
+        if (range) {
+            const int32_t cnt = he - hs;
+            for (int32_t i0 = 0; i0 < cnt; i0 += 4 * 64) {
+                int16_t v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t i = i0 + (int32_t)lane + 64 * u;
+                    v[u] = i < cnt ? a.hits[hs + i] : (int16_t)0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t i = i0 + (int32_t)lane + 64 * u;
+                    if (i < cnt) sh[i] = v[u];
+                }
+            }
+            hbase = (uint32_t)(h0 - hs);
+        } else {
             int16_t v[kRoadsPerWave];
 #pragma unroll
             for (int u = 0; u < kRoadsPerWave; ++u) {
@@ -217,6 +242,7 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
                 const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane(walk ? h1 - h0 : 0, u);
                 if (lane < cnt) sh[u * kRoadHitCap + (int32_t)lane] = v[u];
             }
+            hbase = lane * (uint32_t)kRoadHitCap;
         }
 
         if (walk) {
@@ -249,7 +275,7 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
                 q.chi[k] = make_int4(A[k + 3][0], A[k + 3][1], A[k + 3][2], A[k + 3][3]);
                 q.par[k] = make_int4(A[k][0], A[k][1], A[k][2], A[k][3]);
             }
-            q.zc = make_int4(z[3], z[4], z[5], (int32_t)nh4);
+            q.zc = make_int4(z[3], z[4], z[5], (int32_t)(n0 | n1 << 5 | n2 << 10 | n3 << 15 | hbase << 20));
             q.dec = make_int4((int32_t)start, (int32_t)magic(n1), (int32_t)magic(n2), (int32_t)magic(n3));
             q.pos = make_int4(0, np, (int32_t)(uint32_t)o0, (int32_t)(o0 >> 32));
             q.zp = make_int4(z[0], z[1], z[2], 0);
@@ -272,12 +298,12 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
                 const RoadRec &q = rec[j];
                 const int4 zc = q.zc, dec = q.dec;
                 k = f - (uint32_t)dec.x;
-                const uint32_t m0 = (uint32_t)zc.w & 255u, m1 = ((uint32_t)zc.w >> 8) & 255u,
-                               m2 = ((uint32_t)zc.w >> 16) & 255u, m3 = (uint32_t)zc.w >> 24;
+                const uint32_t w = (uint32_t)zc.w;
+                const uint32_t m0 = w & 31u, m1 = (w >> 5) & 31u, m2 = (w >> 10) & 31u, m3 = (w >> 15) & 31u;
                 const uint32_t q3 = div_small(k, (uint32_t)dec.w), i3 = k - q3 * m3;
                 const uint32_t q2 = div_small(q3, (uint32_t)dec.z), i2 = q3 - q2 * m2;
                 const uint32_t i0 = div_small(q2, (uint32_t)dec.y), i1 = q2 - i0 * m1;
-                const int16_t *hr = sh + j * kRoadHitCap;
+                const int16_t *hr = sh + (w >> 20);
                 x[0] = hr[i0];
                 x[1] = hr[m0 + i1];
                 x[2] = hr[m0 + m1 + i2];

@@ -100,6 +100,49 @@ def test_list_grid_stride(ctx, oracle_lib):
     assert_same_list(got, want, "16500 events: ")
 
 
+def test_list_road_by_road_staging(ctx, oracle_lib):
+    """A malformed road whose hit range is 5000 hits longer than its hits
+    (the later roads' hits shifted behind them): its group of 16 roads cannot
+    stage its hit range at once and stages road by road.  The malformed road
+    is reported, and every other road's entries equal the oracle's list of
+    the unmodified batch."""
+    import torch
+    from paper_1311_0380_amd import svt
+    batch, consts = synth.cfg2(n_events=20)
+    X = 37                                   # inside the group of roads 32..47
+    rc, want, _ = oracle_lib.list_passing_batch(batch, consts)
+    assert rc == 0
+    rc, fit, _ = oracle_lib.fit_batch(batch, consts, n_threads=8)
+    assert rc == 0
+    cut = int(batch.hit_offsets[X + 1])
+    hits = np.concatenate([batch.hits[:cut], np.zeros(5000, np.int16), batch.hits[cut:]])
+    ho = batch.hit_offsets.copy()
+    ho[X + 1:] += 5000
+    mod = synth.Batch(road_offsets=batch.road_offsets, sector=batch.sector, nhits=batch.nhits,
+                      hit_offsets=ho, hits=hits, xft=batch.xft)
+    npass = fit["npass"].astype(np.int32).copy()
+    npass[X] = 0
+    ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+    db = svt.to_device(mod)
+    np_dev = torch.from_numpy(npass).cuda()
+    lst = svt.DevicePassList(mod.n_roads, int(npass.sum()))
+    st, t = svt.svt_list_passing(ctx.handle, db.struct(), np_dev.data_ptr(), lst.struct(),
+                                 torch.cuda.current_stream().cuda_stream)
+    svt.check(st, "svt_list_passing")
+    st, summ = ctx.result(t, -1)
+    assert st == svt.SVT_E_RANGE and summ.err_road == X
+    got = lst.numpy()
+    go, wo = got["offsets"], want["offsets"]
+    assert go[X + 1] == go[X]
+    for r in range(mod.n_roads):
+        if r == X:
+            continue
+        a, b, c, d = int(go[r]), int(go[r + 1]), int(wo[r]), int(wo[r + 1])
+        assert b - a == d - c, r
+        for f in ("k", "chi2", "params"):
+            assert np.array_equal(np.asarray(got[f])[a:b], np.asarray(want[f])[c:d]), (r, f)
+
+
 def test_list_capacity(ctx, oracle_lib):
     """A list that does not fit: SVT_E_RANGE with err_road -1, complete
     offsets, and the entries that fit equal the start of the full list."""
