@@ -70,6 +70,36 @@ __device__ __forceinline__ Agg shfl_up(const Agg &v, int off)
     return o;
 }
 
+// Cross-lane steps of a wavefront inclusive scan (DPP): row shifts by 1, 2,
+// 4 and 8 within rows of 16 lanes, then the last lane of row 0 (2) into
+// rows 1 (3) and the last lane of row 1 into rows 2 and 3.  A lane with no
+// source, or outside the step's rows, receives the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ Agg dpp_move(const Agg &v)
+{
+    Agg o;
+    const uint64_t h = (uint64_t)v.hits;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)h, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(h >> 32), CTRL, ROWS, 0xf, false);
+    o.hits = (int64_t)((uint64_t)hi << 32 | lo);
+    o.ev = __builtin_amdgcn_update_dpp(0, v.ev, CTRL, ROWS, 0xf, false);
+    o.rd = __builtin_amdgcn_update_dpp(0, v.rd, CTRL, ROWS, 0xf, false);
+    o.last_road = __builtin_amdgcn_update_dpp(-1, v.last_road, CTRL, ROWS, 0xf, false);
+    o.last_ev = __builtin_amdgcn_update_dpp(-1, v.last_ev, CTRL, ROWS, 0xf, false);
+    return o;
+}
+
+__device__ __forceinline__ Agg wave_incl(Agg v)
+{
+    v = agg_add(dpp_move<0x111, 0xf>(v), v);   // row_shr:1
+    v = agg_add(dpp_move<0x112, 0xf>(v), v);   // row_shr:2
+    v = agg_add(dpp_move<0x114, 0xf>(v), v);   // row_shr:4
+    v = agg_add(dpp_move<0x118, 0xf>(v), v);   // row_shr:8
+    v = agg_add(dpp_move<0x142, 0xa>(v), v);   // row_bcast:15 into rows 1, 3
+    v = agg_add(dpp_move<0x143, 0xc>(v), v);   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // the kPer words of a thread: one 16-byte load when aligned and whole
 __device__ __forceinline__ void load_words(const uint32_t *src, int64_t base, int64_t n, bool vec,
                                            uint32_t (&w)[kPer])
@@ -88,18 +118,13 @@ __device__ __forceinline__ void load_words(const uint32_t *src, int64_t base, in
 static_assert(kPer == 4, "one 16-byte load per thread");
 
 // Exclusive scan of one Agg per thread across a block of NT threads (thread
-// order), and the block total.  Wavefront shuffles, then the wavefront
+// order), and the block total.  A wavefront scan (DPP), then the wavefront
 // totals in LDS.
 template <int NT>
 __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    Agg incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const Agg o = shfl_up(incl, off);
-        if (lane >= off) incl = agg_add(o, incl);
-    }
+    const Agg incl = wave_incl(v);
     if (lane == 63) s_w[wid] = incl;
     __syncthreads();
     Agg before = kZero, tot = kZero;
@@ -116,21 +141,12 @@ __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
     return agg_add(before, prev);
 }
 
-// Sum of one Agg per thread across the block (wavefront butterflies, then
-// the wavefront sums in LDS); the same in every thread.
-__device__ Agg block_total(Agg v, Agg *s_w)
+// Sum of one Agg per thread across the block (the wavefront scan's last
+// lane, then the wavefront sums in LDS); the same in every thread.
+__device__ Agg block_total(const Agg &v, Agg *s_w)
 {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        Agg o;
-        o.hits = __shfl_xor(v.hits, off, 64);
-        o.ev = __shfl_xor(v.ev, off, 64);
-        o.rd = __shfl_xor(v.rd, off, 64);
-        o.last_road = __shfl_xor(v.last_road, off, 64);
-        o.last_ev = __shfl_xor(v.last_ev, off, 64);
-        v = agg_add(v, o);
-    }
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    const Agg incl = wave_incl(v);
+    if ((threadIdx.x & 63) == 63) s_w[threadIdx.x >> 6] = incl;
     __syncthreads();
     Agg tot = kZero;
 #pragma unroll
