@@ -74,11 +74,38 @@ __device__ __forceinline__ int32_t row(int32_t z, const int4 &c, const int32_t (
     return z + __mul24(c.x, x[0]) + __mul24(c.y, x[1]) + __mul24(c.z, x[2]) + __mul24(c.w, x[3]);
 }
 
+// A 64-bit value from another lane by DPP: CTRL is row_shr:n (0x110 + n),
+// row_bcast:15 (0x142) or row_bcast:31 (0x143); lanes with no source, or
+// outside the rows in ROWS, receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int64_t dpp64(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, false);
+    return (int64_t)((uint64_t)hi << 32 | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+
+// Sum across the wavefront (all lanes active), as a uniform value: an
+// inclusive DPP scan, then lane 63.
 __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp64<0x111, 0xf>(v);
+    v += dpp64<0x112, 0xf>(v);
+    v += dpp64<0x114, 0xf>(v);
+    v += dpp64<0x118, 0xf>(v);
+    v += dpp64<0x142, 0xa>(v);
+    v += dpp64<0x143, 0xc>(v);
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return (int64_t)((uint64_t)hi << 32 | lo);
 }
 
 __global__ void __launch_bounds__(kBlock) list_tile_sums(const int32_t *npass, int32_t n, int64_t *tsum)
@@ -186,18 +213,19 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
         const bool walk = ok && np > 0;
         const uint32_t nc = walk ? n0 * n1 * n2 * n3 : 0u;
 
-        // list offsets and first slots: running sums of npass and nc over lanes 0..15
+        // list offsets and first slots: running sums of npass and nc over
+        // lanes 0..15 (DPP row shifts within the first row of 16 lanes)
+        static_assert(kRoadsPerWave == 16, "one DPP row");
         int64_t po = np;
         uint32_t incl = nc;
-#pragma unroll
-        for (int d = 1; d < kRoadsPerWave; d <<= 1) {
-            const int64_t p = __shfl_up(po, d, kRoadsPerWave);
-            const uint32_t o = (uint32_t)__shfl_up((int)incl, d, kRoadsPerWave);
-            if ((lane & (kRoadsPerWave - 1)) >= (uint32_t)d) {
-                po += p;
-                incl += o;
-            }
-        }
+        po += dpp64<0x111, 0xf>(po);
+        incl += dpp32<0x111>(incl);
+        po += dpp64<0x112, 0xf>(po);
+        incl += dpp32<0x112>(incl);
+        po += dpp64<0x114, 0xf>(po);
+        incl += dpp32<0x114>(incl);
+        po += dpp64<0x118, 0xf>(po);
+        incl += dpp32<0x118>(incl);
         const int64_t o0 = before + po - np;
         if (inr) a.offsets[r] = o0;
         const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kRoadsPerWave - 1);
