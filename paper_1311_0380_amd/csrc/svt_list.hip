@@ -92,9 +92,8 @@ __device__ __forceinline__ uint32_t dpp32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
 }
 
-// Sum across the wavefront (all lanes active), as a uniform value: an
-// inclusive DPP scan, then lane 63.
-__device__ __forceinline__ int64_t wave_sum64(int64_t v)
+// Inclusive running sum across the wavefront (all lanes active), by DPP.
+__device__ __forceinline__ int64_t wave_incl64(int64_t v)
 {
     v += dpp64<0x111, 0xf>(v);
     v += dpp64<0x112, 0xf>(v);
@@ -102,7 +101,13 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
     v += dpp64<0x118, 0xf>(v);
     v += dpp64<0x142, 0xa>(v);
     v += dpp64<0x143, 0xc>(v);
-    const uint64_t u = (uint64_t)v;
+    return v;
+}
+
+// Sum across the wavefront (all lanes active), as a uniform value.
+__device__ __forceinline__ int64_t wave_sum64(int64_t v)
+{
+    const uint64_t u = (uint64_t)wave_incl64(v);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
     return (int64_t)((uint64_t)hi << 32 | lo);
@@ -141,12 +146,7 @@ __global__ void __launch_bounds__(kBlock) list_tile_scan(int64_t *tsum, int32_t 
     for (int32_t b0 = 0; b0 < n_tiles; b0 += kBlock) {
         const int32_t b = b0 + threadIdx.x;
         const int64_t v = b < n_tiles ? tsum[b] : 0;
-        int64_t incl = v;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int64_t t = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += t;
-        }
+        const int64_t incl = wave_incl64(v);
         if (lane == 63) s_w[wid] = incl;
         __syncthreads();
         int64_t before = 0, tot = 0;
