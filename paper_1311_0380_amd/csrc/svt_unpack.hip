@@ -59,21 +59,11 @@ __device__ __forceinline__ Agg agg_add(const Agg &x, const Agg &y)
                max(x.last_ev, y.last_ev)};
 }
 
-__device__ __forceinline__ Agg shfl_up(const Agg &v, int off)
-{
-    Agg o;
-    o.hits = __shfl_up(v.hits, off, 64);
-    o.ev = __shfl_up(v.ev, off, 64);
-    o.rd = __shfl_up(v.rd, off, 64);
-    o.last_road = __shfl_up(v.last_road, off, 64);
-    o.last_ev = __shfl_up(v.last_ev, off, 64);
-    return o;
-}
-
-// Cross-lane steps of a wavefront inclusive scan (DPP): row shifts by 1, 2,
-// 4 and 8 within rows of 16 lanes, then the last lane of row 0 (2) into
-// rows 1 (3) and the last lane of row 1 into rows 2 and 3.  A lane with no
-// source, or outside the step's rows, receives the identity.
+// Cross-lane moves by DPP for a wavefront inclusive scan: row shifts by 1,
+// 2, 4 and 8 within rows of 16 lanes, then the last lane of row 0 (2) into
+// row 1 (3) and the last lane of row 1 into rows 2 and 3; and wave_shr:1
+// (0x138), each lane's predecessor.  A lane with no source, or outside the
+// move's rows, receives the identity.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ Agg dpp_move(const Agg &v)
 {
@@ -135,10 +125,9 @@ __device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
     }
     __syncthreads();
     total = tot;
-    // exclusive = before + (inclusive of this lane's predecessors)
-    Agg prev = shfl_up(incl, 1);
-    if (lane == 0) prev = kZero;
-    return agg_add(before, prev);
+    // exclusive = before + (inclusive of this lane's predecessor; lane 0
+    // receives the identity): DPP wave_shr:1
+    return agg_add(before, dpp_move<0x138, 0xf>(incl));
 }
 
 // Sum of one Agg per thread across the block (the wavefront scan's last
