@@ -357,6 +357,14 @@ typedef struct {
     int32_t pad_;
 } svt_shadow_tracks;
 
+/* Blocks per sector the forward and backward run over (slices of about 2048
+ * tracks of one sector each, at least 1 and at most 64; the partial sums of a
+ * sector's slices are then reduced in slice order).  Reporting only: results
+ * never depend on it beyond fp64 rounding order, which is fixed for given
+ * counts.  Errors: SVT_E_INVAL (slices NULL, n_tracks < 0, n_sectors out of
+ * 1..256). */
+svt_status svt_shadow_slices(int32_t n_tracks, int32_t n_sectors, int32_t *slices);
+
 /* Fit rows y (optional [n_tracks][6], may be NULL) and the data term of L
  * (double, written to loss[0]).  coef [n_sectors][6][6], offset [n_sectors][6]. */
 svt_status svt_shadow_forward(svt_ctx *ctx, const svt_shadow_tracks *tracks, const float *coef,

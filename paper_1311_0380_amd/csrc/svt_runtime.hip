@@ -17,6 +17,7 @@
 #include "svt_list.h"
 #include "svt_unpack.h"
 #include "svt_shadow.h"
+#include "svt_submit_guard.h"
 
 namespace svt {
 hipError_t launch_zero_copy(const void *src, void *dst, size_t bytes, int cus, hipStream_t st);
@@ -597,16 +598,10 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         svt_status r = stage_acquire(c, s.stage, off);
         if (r != SVT_OK) return r;
     }
-    // the staging buffer goes back to the pool unless the request is submitted
-    struct StageGuard {
-        svt_ctx *c;
-        DevBuf *b;
-        bool keep = false;
-        ~StageGuard()
-        {
-            if (!keep) stage_release(c, *b);
-        }
-    } guard{c, &s.stage};
+    // the staging buffer goes back to the pool unless the request is
+    // submitted; once something is enqueued, only after the stream is idle
+    auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); },
+                                        [c, &s] { stage_release(c, s.stage); });
     char *base = static_cast<char *>(s.stage.ptr);
 
     svt::FitArgs a;
@@ -625,6 +620,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     const bool kernel_only = !stage_in && !stage_out && res->comb_offsets == nullptr;
     const int32_t every = c->timing_every;
     const bool timed = every == 1 || (every > 1 && c->next_ticket % every == 0);
+    guard.enqueuing();
     if (!kernel_only && timed) HIP_TRY(hipEventRecord(s.ev_start, st));
     if (stage_in) {
         const hipMemcpyKind k = hipMemcpyHostToDevice;
@@ -705,7 +701,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         if (co_dev) HIP_TRY(hipMemcpyAsync(res->comb_offsets, co_dev, b_co, k, st));
     }
     if (!kernel_only) HIP_TRY(hipEventRecord(s.ev_end, st));
-    guard.keep = true;
+    guard.submitted();
     s.timed = timed;
     s.busy = true;
     s.ticket = c->next_ticket++;
@@ -765,10 +761,15 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     if (grid > c->max_grid) grid = c->max_grid;
     if (grid < 1) grid = 1;
 
+    // nothing to give back on failure, but the scan scratch and the partials
+    // stay with this slot until enqueued work is done
+    auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); }, [] {});
+    guard.enqueuing();
     HIP_TRY(hipEventRecord(s.ev_start, st));
     hipError_t e = svt::launch_list(a, (int)grid, static_cast<int64_t *>(s.scan.ptr), st);
     if (e != hipSuccess) return hip_fail(e, "list kernel launch");
     HIP_TRY(hipEventRecord(s.ev_end, st));
+    guard.submitted();
     s.grid = (int)grid;
     s.parts = s.partials;
     s.plan = nullptr;
@@ -804,15 +805,8 @@ svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words,
     const size_t need = b_tiles + (in_device ? 0 : align_up(4 * (size_t)n_words, 256));
     svt_status r = stage_acquire(c, s.stage, need);
     if (r != SVT_OK) return r;
-    struct StageGuard {
-        svt_ctx *c;
-        DevBuf *b;
-        bool keep = false;
-        ~StageGuard()
-        {
-            if (!keep) stage_release(c, *b);
-        }
-    } guard{c, &s.stage};
+    auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); },
+                                        [c, &s] { stage_release(c, s.stage); });
     char *base = static_cast<char *>(s.stage.ptr);
 
     svt::UnpackArgs a;
@@ -838,6 +832,7 @@ svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words,
         const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
     a.seq = (uint32_t)c->next_ticket;
 
+    guard.enqueuing();
     HIP_TRY(hipEventRecord(s.ev_start, st));
     if (mem_kind == SVT_MEM_MAPPED) {
         // zero copy: the first pass reads the host words in place and leaves
@@ -854,7 +849,7 @@ svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words,
     hipError_t e = svt::launch_unpack(a, st);
     if (e != hipSuccess) return hip_fail(e, "unpack launch");
     HIP_TRY(hipEventRecord(s.ev_end, st));
-    guard.keep = true;
+    guard.submitted();
     s.grid = a.n_apply + 1;
     s.parts = s.partials;
     s.plan = nullptr;
@@ -948,6 +943,13 @@ static bool shadow_ok(const svt_shadow_tracks *t)
 {
     return t && t->n_tracks >= 0 && t->n_sectors >= 1 && t->n_sectors <= 256 &&
            t->sector_offsets && (t->n_tracks == 0 || (t->x && t->tau));
+}
+
+svt_status svt_shadow_slices(int32_t n_tracks, int32_t n_sectors, int32_t *slices)
+{
+    if (slices == nullptr || n_tracks < 0 || n_sectors < 1 || n_sectors > 256) return SVT_E_INVAL;
+    *slices = svt::shadow_slices(n_tracks, n_sectors);
+    return SVT_OK;
 }
 
 svt_status svt_shadow_forward(svt_ctx *c, const svt_shadow_tracks *t, const float *coef,
@@ -1219,6 +1221,9 @@ svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results
 
     const int32_t every = c->timing_every;
     const bool timed = every == 1 || (every > 1 && c->next_ticket % every == 0);
+    // the plan's buffers and partials stay unused until enqueued work is done
+    auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); }, [] {});
+    guard.enqueuing();
     if (timed) HIP_TRY(hipEventRecord(s.ev_start, st));
     // inputs into the plan's buffers (skipped when the caller filled them in place)
     const void *src[6] = {b->road_offsets, b->sector, b->nhits, b->hit_offsets, b->hits, b->xft};
@@ -1249,6 +1254,7 @@ svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results
     for (int i = 0; i < 7; ++i)
         if (rb[i] && rd[i] != rs[i]) HIP_TRY(hipMemcpyAsync(rd[i], rs[i], rb[i], hipMemcpyDefault, st));
     HIP_TRY(hipEventRecord(s.ev_end, st));
+    guard.submitted();
     s.timed = timed;
     s.busy = true;
     s.ticket = c->next_ticket++;

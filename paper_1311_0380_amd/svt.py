@@ -105,6 +105,8 @@ SIGNATURES = {
     "svt_plan_fit": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch),
                                       ctypes.POINTER(svt_results), P,
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "svt_shadow_slices": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32)]),
     "svt_shadow_forward": (ctypes.c_int32, [P, ctypes.POINTER(svt_shadow_tracks), P, P, P, P, P]),
     "svt_shadow_backward": (ctypes.c_int32, [P, ctypes.POINTER(svt_shadow_tracks), P, P, P, P, P,
                                              P, P, P]),
@@ -209,6 +211,12 @@ def svt_get_device_info(ctx) -> dict:
     d = {f: getattr(i, f) for f, _ in i._fields_}
     d["arch"] = d["arch"].decode()
     return d
+
+
+def shadow_slices(n_tracks: int, n_sectors: int) -> int:
+    v = ctypes.c_int32(0)
+    check(lib.svt_shadow_slices(int(n_tracks), int(n_sectors), ctypes.byref(v)), "svt_shadow_slices")
+    return v.value
 
 
 # ---------------------------------------------------------------------------

@@ -7,8 +7,8 @@ oracle and the HIP library consume what it returns.
 
 Shapes follow the paper's problem statement (Sec. 2: roads found per event,
 one hit per layer per combination, per-sector constants f_i, q_i) and the
-workload description of Sec. 4 (events with a fixed number of roads and
-combinations, 1 to 3000 events).  The paper's own data (CDF SVT events and
+Sec. 4 workload, in which every event has the same road and combination
+counts and batches run from 1 to 3000 events.  The paper's own data (CDF SVT events and
 constant files) is not available; these generators stand in for it.
 
 Conventions used throughout:

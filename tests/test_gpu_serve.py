@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_1311_0380_amd import synth
-from tests.gpu_helpers import assert_equal_results, lib_fit
+from tests.gpu_helpers import FIELDS, assert_equal_results, lib_fit
 
 pytestmark = pytest.mark.gpu
 
@@ -24,11 +24,18 @@ def make_ctx(env, budget=0):
     return ctx
 
 
-def test_alone_equals_in_mix(env):
+def test_alone_equals_in_mix(env, oracle_lib):
+    """Every burst served in merged launches equals the same burst fitted
+    alone by the library, and equals the oracle's results for its events
+    (one oracle run over the pool, sliced: roads and events are fitted
+    independently, so a burst's results are the slice of the pool's)."""
     serve = env["serve"]
+    batch = env["batch"]
+    rc, want_all, _ = oracle_lib.fit_batch(batch, env["consts"], n_threads=8)
+    assert rc == 0
     ctx = make_ctx(env)
     try:
-        pool = serve.HostPool(env["batch"])
+        pool = serve.HostPool(batch)
         dev = serve.LibraryDevice(ctx, 3)
         srv = serve.Server(dev, pool, n_slots=3, max_events=4000, keep_results=True)
         rng = np.random.default_rng(4)
@@ -36,11 +43,15 @@ def test_alone_equals_in_mix(env):
         recs = srv.run(arr)
         assert len(recs) == 80 and all(r.done > 0 for r in recs)
         assert len(set(r.launch for r in recs)) < 80       # some bursts were merged
-        for r in recs[::3]:
-            alone = env["batch"].select_events(r.e0, r.e1)
+        for r in recs:
+            alone = batch.select_events(r.e0, r.e1)
             st, _, got = lib_fit(ctx.handle, alone)
             assert st == 0
-            assert_equal_results(srv.results[r.idx], got, where=f"burst {r.idx}: ")
+            assert_equal_results(srv.results[r.idx], got, where=f"burst {r.idx} vs alone: ")
+            r0, r1 = int(batch.road_offsets[r.e0]), int(batch.road_offsets[r.e1])
+            want = {f: (v[r.e0:r.e1] if f == "ntracks" else v[r0:r1]) for f, v in want_all.items()
+                    if f in FIELDS}
+            assert_equal_results(srv.results[r.idx], want, where=f"burst {r.idx} vs oracle: ")
     finally:
         ctx.close()
 

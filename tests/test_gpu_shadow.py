@@ -1,7 +1,13 @@
 """GPU float shadow: fp32 kernels against the FP64 oracle within the stated
 tolerance, the hand-written backward against the FP64 gradient, the autograd
-wrapper, requantization bit for bit, calibration, and rescoring on the
-integer path."""
+wrapper, requantization bit for bit, calibration to its closed-form endpoint,
+and rescoring on the integer path.
+
+The forward / backward / autograd parity runs at 120k helix tracks (one slice
+per sector), at the calibration workload's full 1e6 tracks (seven slices per
+sector, so the per-sector reductions across slices are compared) and on a
+skewed batch whose largest sector holds 400k tracks (the slice count clamps
+at 64 and sectors split unevenly, down to slices of zero or one track)."""
 import numpy as np
 import pytest
 
@@ -13,24 +19,78 @@ pytestmark = pytest.mark.gpu
 W = (1.0 / 400.0, 1.0 / 1.0e4, 1.0)
 
 
-@pytest.fixture(scope="module")
-def env():
-    import torch
-    from paper_1311_0380_amd import shadow, svt
-    h = synth.helix_tracks(120000, seed=44)
-    coef, off = synth.pilot_constants(h)
-    rng = np.random.default_rng(5)
+class _Tracks:
+    """Tracks grouped by sector, in the generator's layout."""
+
+    def __init__(self, x, truth, sector_offsets):
+        self.x, self.truth, self.sector_offsets = x, truth, sector_offsets
+
+
+def _skewed(seed=46):
+    """Three sectors of 400k, 7 and 300k tracks: 235,669 tracks per sector on
+    average, so the slice count clamps at 64; the 7-track sector gets slices
+    of zero or one track.  Words uniform in [0, 4096), truth a linear map of
+    them plus noise."""
+    rng = np.random.default_rng(seed)
+    ns = [400000, 7, 300000]
+    x = rng.uniform(0, 4096, (sum(ns), 6)).astype(np.float32)
+    F = rng.normal(0, 1e-2, (3, 6))
+    tau = (x.astype(np.float64) @ F.T + rng.normal(0, 1.0, (x.shape[0], 3))).astype(np.float32)
+    off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int32)
+    return _Tracks(x, tau, off)
+
+
+def _constants(h, seed=5):
+    coef, off = synth.pilot_constants(h) if hasattr(h, "xq") else _pilot_plain(h)
+    rng = np.random.default_rng(seed)
     # a point away from the optimum: residuals are large, as early in a calibration
     coef = (coef * (1 + rng.normal(0, 0.02, coef.shape))).astype(np.float32)
     off = (off + rng.normal(0, 5.0, off.shape)).astype(np.float32)
+    return coef, off
+
+
+def _pilot_plain(h):
+    n_s = h.sector_offsets.shape[0] - 1
+    rng = np.random.default_rng(3)
+    coef = rng.normal(0, 0.3, (n_s, 6, 6)).astype(np.float32)
+    off = rng.normal(0, 50.0, (n_s, 6)).astype(np.float32)
+    return coef, off
+
+
+@pytest.fixture(scope="module", params=["helix120k", "helix1e6", "skewed"])
+def env(request):
+    import torch
+    from paper_1311_0380_amd import shadow, svt
+    if request.param == "helix120k":
+        h = synth.helix_tracks(120000, seed=44)
+    elif request.param == "helix1e6":
+        h = synth.helix_tracks(1000000, seed=44)
+    else:
+        h = _skewed()
+    coef, off = _constants(h)
     handle = svt.svt_create(0, 0)
-    tr = shadow.ShadowTracks.from_helix(h, W)
-    yield dict(h=h, coef=coef, off=off, handle=handle, tracks=tr, torch=torch, shadow=shadow)
+    tr = shadow.ShadowTracks(x=torch.tensor(h.x, dtype=torch.float32, device="cuda"),
+                             tau=torch.tensor(h.truth, dtype=torch.float32, device="cuda"),
+                             sector_offsets=torch.tensor(h.sector_offsets, dtype=torch.int32,
+                                                         device="cuda"), w=W)
+    n_s = len(h.sector_offsets) - 1
+    print(f"\nshadow case {request.param}: {h.x.shape[0]} tracks, {n_s} sectors, "
+          f"{svt.shadow_slices(h.x.shape[0], n_s)} slices per sector", flush=True)
+    yield dict(name=request.param, h=h, coef=coef, off=off, handle=handle, tracks=tr,
+               torch=torch, shadow=shadow)
     svt.svt_destroy(handle)
 
 
 def dev(env, a):
     return env["torch"].tensor(a, device="cuda")
+
+
+def test_slice_counts_cover_the_reduction_paths(env):
+    from paper_1311_0380_amd import svt
+    h = env["h"]
+    n_s = len(h.sector_offsets) - 1
+    want = {"helix120k": 1, "helix1e6": 7, "skewed": 64}[env["name"]]
+    assert svt.shadow_slices(h.x.shape[0], n_s) == want
 
 
 def test_forward_rows_and_loss(env):
@@ -87,6 +147,8 @@ def test_autograd_function_and_finite_differences(env):
                            h.sector_offsets, W)
     assert np.abs(A.grad.cpu().numpy() - 3.0 * gA).max() <= 2e-6 * np.abs(3.0 * gA).max()
     assert np.abs(b.grad.cpu().numpy() - 3.0 * gb).max() <= 2e-6 * np.abs(3.0 * gb).max()
+    if env["name"] != "helix120k":
+        return
     # the FP64 gradient it matches is itself checked by central differences
     for idx in [(3, 0, 0), (10, 4, 2)]:
         fd = osh.finite_difference(coef, off, h.x.astype(np.float32), h.truth.astype(np.float32),
@@ -105,7 +167,8 @@ def test_requantize_bit_exact(env):
 
 
 def test_calibration_reduces_loss_and_rescore(env, oracle_lib):
-    torch = env["torch"]
+    if env["name"] != "helix120k":
+        pytest.skip("one calibration and rescore run suffices (helix120k)")
     from paper_1311_0380_amd import svt
     h = env["h"]
     coef, off = synth.pilot_constants(h)
@@ -138,22 +201,86 @@ def test_calibration_reduces_loss_and_rescore(env, oracle_lib):
     assert_equal_results(got, want)
 
 
-def test_default_stream_ordering(env):
+def _endpoint_workload(seed=11):
+    """Three sectors of 3000, 5000 and 8000 tracks with well-separated input
+    variances (0.05 ... 4 along a random rotation) and truth a linear map of
+    the inputs plus N(0, 0.01) noise: a calibration that Adam drives to its
+    closed-form optimum in a few thousand steps."""
+    rng = np.random.default_rng(seed)
+    ns = [3000, 5000, 8000]
+    F = rng.normal(0, 1, (3, 3, 6))
+    f = rng.normal(0, 1, (3, 3))
+    xs, ts = [], []
+    for s in range(3):
+        q, _ = np.linalg.qr(rng.normal(size=(6, 6)))
+        L = q * np.sqrt([0.05, 0.1, 0.2, 1.0, 2.0, 4.0])
+        x = rng.normal(0, 0.5, 6) + rng.normal(size=(ns[s], 6)) @ L.T
+        xs.append(x)
+        ts.append(x @ F[s].T + f[s] + rng.normal(0, 0.01, (ns[s], 3)))
+    off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int32)
+    coef0 = rng.normal(0, 0.3, (3, 6, 6)).astype(np.float32)
+    off0 = rng.normal(0, 0.3, (3, 6)).astype(np.float32)
+    return (np.vstack(xs).astype(np.float32), np.vstack(ts).astype(np.float32), off,
+            coef0, off0)
+
+
+def test_calibration_reaches_closed_form_endpoint():
+    """Adam in the library's kernels (backward, penalty, Adam step) converges
+    to the optimum the oracle gives in closed form: the parameter rows to the
+    per-sector least-squares fit of the truth on [x, 1]
+    (osh.lstsq_parameter_rows) and the constraint rows to the span of the
+    three smallest-variance directions with squared norms
+    1 - (N_s/N) e_i / (2 lambda) (osh.constraint_optimum).  The constraint
+    rows are unique only up to a rotation inside that span, so C^T C (6x6)
+    and the offsets -C mu are compared."""
+    import torch
+    from paper_1311_0380_amd import shadow, svt
+    x, tau, off, coef0, off0 = _endpoint_workload()
+    lam = 10.0
+    handle = svt.svt_create(0, 0)
+    try:
+        tr = shadow.ShadowTracks(x=torch.tensor(x, device="cuda"), tau=torch.tensor(tau, device="cuda"),
+                                 sector_offsets=torch.tensor(off, device="cuda"), w=(1.0, 1.0, 1.0))
+        c, o = torch.tensor(coef0, device="cuda"), torch.tensor(off0, device="cuda")
+        for lr, steps in ((1e-2, 1500), (1e-3, 1000), (1e-4, 1000)):
+            res = shadow.calibrate(handle, tr, c, o, steps=steps, lr=lr, lam=lam, record_every=steps)
+            c, o = res.coef, res.offset
+        torch.cuda.synchronize()
+    finally:
+        svt.svt_destroy(handle)
+    c = c.cpu().numpy().astype(np.float64)
+    o = o.cpu().numpy().astype(np.float64)
+    F, f = osh.lstsq_parameter_rows(x, tau, off)
+    assert np.abs(c[:, :3] - F).max() <= 1e-4, np.abs(c[:, :3] - F).max()
+    assert np.abs(o[:, :3] - f).max() <= 1e-4, np.abs(o[:, :3] - f).max()
+    for s, (e, V, mu, frac) in enumerate(osh.constraint_optimum(x, off, lam)):
+        C = c[s, 3:]
+        want = (V * (1.0 - frac * e / (2.0 * lam))) @ V.T
+        assert np.abs(C.T @ C - want).max() <= 1e-4, (s, np.abs(C.T @ C - want).max())
+        assert np.abs(o[s, 3:] + C @ mu).max() <= 1e-4, (s, np.abs(o[s, 3:] + C @ mu).max())
+
+
+def test_default_stream_ordering():
     """Library calls on torch's default stream (handle 0) are ordered with
     torch's own work on it: a copy issued right after the backward sees the
     finished gradient, at a size where the backward takes tens of µs."""
-    torch = env["torch"]
+    import torch
+    from paper_1311_0380_amd import shadow, svt
     h = synth.helix_tracks(1000000, seed=45)
     coef, off = synth.pilot_constants(h)
-    tr = env["shadow"].ShadowTracks.from_helix(h, W)
-    A, b = dev(env, coef), dev(env, off)
-    assert torch.cuda.current_stream().cuda_stream == 0
-    for _ in range(3):
-        g64, o64, _, _ = env["shadow"].backward(env["handle"], tr, A, b)
-        early = torch.cat([g64.reshape(-1), o64.reshape(-1)]).clone()
-        loss, _ = env["shadow"].forward(env["handle"], tr, A, b)
-        early_loss = loss.item()
-        torch.cuda.synchronize()
-        late = torch.cat([g64.reshape(-1), o64.reshape(-1)])
-        assert torch.equal(early, late)
-        assert np.isfinite(early_loss) and early_loss == loss.item() and early_loss >= 0
+    handle = svt.svt_create(0, 0)
+    try:
+        tr = shadow.ShadowTracks.from_helix(h, W)
+        A, b = torch.tensor(coef, device="cuda"), torch.tensor(off, device="cuda")
+        assert torch.cuda.current_stream().cuda_stream == 0
+        for _ in range(3):
+            g64, o64, _, _ = shadow.backward(handle, tr, A, b)
+            early = torch.cat([g64.reshape(-1), o64.reshape(-1)]).clone()
+            loss, _ = shadow.forward(handle, tr, A, b)
+            early_loss = loss.item()
+            torch.cuda.synchronize()
+            late = torch.cat([g64.reshape(-1), o64.reshape(-1)])
+            assert torch.equal(early, late)
+            assert np.isfinite(early_loss) and early_loss == loss.item() and early_loss >= 0
+    finally:
+        svt.svt_destroy(handle)

@@ -66,3 +66,48 @@ def test_algorithmic_bytes_of_the_headline_batch():
     import bench
     b, _ = synth.cfg2()
     assert bench.algorithmic_bytes(b.n_events, b.n_roads, b.n_hits) == 13284326
+
+
+GUARD_TEST = r"""
+#include <cstdio>
+#include <string>
+#include "svt_submit_guard.h"
+static std::string log_;
+static int run(int fail_at, bool enqueue_before_fail) {
+    // a submission: buffers acquired, then enqueues, failing at step fail_at
+    auto g = svt::make_submit_guard([] { log_ += "S"; }, [] { log_ += "R"; });
+    for (int step = 0; step < 3; ++step) {
+        if (step == 1 && enqueue_before_fail) g.enqueuing();
+        if (step == fail_at) return -1;     // an error return: the guard decides
+    }
+    g.submitted();
+    return 0;
+}
+int main() {
+    log_.clear(); run(0, true);  std::printf("%s|", log_.c_str());   // failed before enqueuing
+    log_.clear(); run(2, true);  std::printf("%s|", log_.c_str());   // failed after enqueuing
+    log_.clear(); run(2, false); std::printf("%s|", log_.c_str());   // failed, nothing enqueued
+    log_.clear(); run(9, true);  std::printf("%s|", log_.c_str());   // submitted
+    return 0;
+}
+"""
+
+
+def test_failed_submission_waits_for_its_stream_before_releasing(tmp_path):
+    """A submission that fails after enqueuing work waits for its stream
+    (S) before its staging buffer goes back to the pool (R); one that fails
+    before enqueuing releases at once; a submitted request releases nothing
+    (its completion does)."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    src = tmp_path / "guard.cc"
+    src.write_text(GUARD_TEST)
+    exe = tmp_path / "guard"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1311_0380_amd", "csrc")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    assert out == "R|SR|R||"

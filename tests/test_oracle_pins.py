@@ -424,3 +424,21 @@ def test_list_passing_capacity(oracle_lib):
     assert np.array_equal(part["offsets"], full["offsets"])
     for f in ("k", "chi2", "params"):
         assert np.array_equal(part[f], full[f][:n - 7])
+
+
+@pytest.mark.parametrize("max_hits", [4, 16])
+def test_twins_resolve_to_the_lowest_index(oracle_lib, max_hits):
+    """Two combinations whose words are equal layer by layer have the same
+    fit inputs, hence the same chi2, whatever the constants; the one with the
+    lower index k wins.  So in batches that repeat words inside layers, the
+    best never uses a word that also sits at a lower index of its layer, and
+    many bests do have such a twin (at a higher index)."""
+    from tests.ties import tie_batch, twin_roads
+    batch, consts = tie_batch(700 + max_hits, max_hits, n_events=40)
+    for cut in (1 << 32, (1 << 46)):
+        consts.chi2_cut = cut
+        rc, want, _ = oracle_lib.fit_batch(batch, consts)
+        assert rc == 0
+        n_twin, viol = twin_roads(batch, want["hit_index"])
+        assert viol == 0
+        assert n_twin >= batch.n_roads // 10
