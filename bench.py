@@ -1,17 +1,21 @@
 """Benchmark of the SVT linearized fit on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
-                [--sections fit,list,unpack,uneven,serve,io,shadow]
+                [--sections fit,sweep,list,unpack,uneven,serve,io,shadow]
 
-Headline step = one svt_fit_events request over the scaled-up plain-fit
-workload (3000 events x 64 roads, 1-4 hits per layer, 72 sectors, lattice
-constants, half the roads with a planted track: 192,000 roads, ~7.5 M
-combinations), inputs and results resident in HBM.  Inputs rotate over
-distinct copies so timed passes read HBM rather than the 256 MB last-level
-cache.  Further sections measure the list of every passing combination,
-the unpack of a packed word stream, the uneven-batch plan against per-event launches, the serving loop (p50/p99
-per burst, batched against plain), the transfer study and the float shadow.
-Prints one JSON line.
+Headline step = one pass of the fit over the scaled-up plain-fit workload
+(3000 events x 64 roads, 1-4 hits per layer, 72 sectors, lattice constants,
+half the roads with a planted track: 192,000 roads, ~7.5 M combinations),
+inputs and results resident in HBM.  The K timed passes run back to back as
+captured graph launches of up to 100 passes (rings), and rotate over 32
+input copies so that they read HBM rather than the 256 MB last-level cache.
+The per-request form (one svt_fit_events call per pass) is reported beside
+it.  Further sections: the paper's sweep (1-3000 events x 2048 combinations,
+with the oracle on one and on all host threads), the list of every passing
+combination, the unpack of a packed word stream, the uneven-batch plan
+against per-event launches, the serving loop (p50/p99 per burst, batched
+against plain), the transfer study and the float shadow.  Prints one JSON
+line.
 """
 from __future__ import annotations
 
@@ -73,26 +77,117 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a, dtype=np.float64), q))
 
 
-def cpu_baseline(batch, consts, min_seconds=10.0, max_reps=5000):
+def host_cpu():
+    """The host's CPU as the oracle sees it: model name, logical CPUs, the
+    CPUs this process may run on, and the threads an OpenMP run uses (the
+    affinity set, capped by OMP_NUM_THREADS when that is set: a GPU job's
+    share of a shared host)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    threads = affinity
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        threads = min(threads, int(omp))
+    return {"model": model, "nproc": os.cpu_count() or 1, "affinity": affinity,
+            "threads": max(1, threads)}
+
+
+def oracle_rate(batch, consts, threads, min_seconds, min_reps=3, max_reps=100):
+    """Oracle passes over one batch until min_seconds have passed (at least
+    min_reps, at most max_reps); returns (combinations/s, median seconds per
+    pass, passes)."""
     import oracle
-    oracle.build(force=False)
-    threads = max(1, min(16, os.cpu_count() or 1))
-    total = reps = 0
-    t0 = time.perf_counter()
-    while reps < max_reps:
+    times, total = [], 0
+    t_all = time.perf_counter()
+    while len(times) < max_reps:
+        t0 = time.perf_counter()
         rc, _, summ = oracle.fit_batch(batch, consts, n_threads=threads, comb_offsets=False)
+        times.append(time.perf_counter() - t0)
         assert rc == 0
         total += summ["total_comb"]
-        reps += 1
-        if time.perf_counter() - t0 >= min_seconds and reps >= 3:
+        if time.perf_counter() - t_all >= min_seconds and len(times) >= min_reps:
             break
-    dt = time.perf_counter() - t0
-    return {"value": total / dt, "unit": "combinations/s", "cores": threads, "kind": "oracle",
-            "sample": f"the full 3000-event batch, {reps} passes in {dt:.1f} s "
-                      f"(OpenMP over events, {threads} threads)"}
+    return total / sum(times), float(np.median(times)), len(times)
+
+
+def cpu_baseline(batch, consts, min_seconds=10.0):
+    """The oracle on the host: all the threads this process may use over the
+    full 3000-event batch, and one thread over its first 300 events."""
+    import oracle
+    oracle.build(force=False)
+    cpu = host_cpu()
+    rate, med, reps = oracle_rate(batch, consts, cpu["threads"], min_seconds)
+    sub = batch.select_events(0, 300)
+    rate1, med1, reps1 = oracle_rate(sub, consts, 1, min_seconds / 2)
+    return {"value": rate, "unit": "combinations/s", "cores": cpu["threads"], "kind": "oracle",
+            "sample": f"the full 3000-event batch, {reps} passes, median {med * 1e3:.0f} ms per pass "
+                      f"(OpenMP over events, {cpu['threads']} threads)",
+            "single_thread": {"value": rate1, "unit": "combinations/s", "cores": 1,
+                              "sample": f"the batch's first 300 events, {reps1} passes, median "
+                                        f"{med1 * 1e3:.1f} ms per pass"},
+            "cpu_model": cpu["model"], "nproc": cpu["nproc"], "affinity": cpu["affinity"]}
+
+
+def make_rings(svt, ctx, bs, rs, steps, per_ring):
+    """Rings covering `steps` passes: full rings of per_ring passes (each
+    starting at a different copy) and one ring for the remainder."""
+    sizes = [per_ring] * (steps // per_ring) + ([steps % per_ring] if steps % per_ring else [])
+    rings = []
+    for i, n in enumerate(sizes):
+        rot = (i * per_ring) % len(bs)
+        order = list(range(rot, len(bs))) + list(range(rot))
+        nb = min(n, len(bs))
+        st, ring = svt.svt_ring_create(ctx, [bs[j] for j in order[:nb]], [rs[j] for j in order[:nb]], n)
+        svt.check(st, "svt_ring_create")
+        rings.append((ring, n))
+    return rings
+
+
+def run_rings(svt, ctx, rings, stream, repeat=1):
+    """Replay the rings in order, at most three runs in flight (a ring runs
+    once at a time); returns (combinations, device ns per run)."""
+    pend, total, dev = collections.deque(), 0, []
+    for _ in range(repeat):
+        for ring, n in rings:
+            st, t = svt.svt_ring_run(ring, stream)
+            while st == svt.SVT_E_AGAIN and pend:   # this ring's previous run is in flight
+                st2, s = svt.svt_result(ctx, pend.popleft(), -1)
+                svt.check(st2, "ring")
+                total += s.total_comb
+                dev.append(s.device_ns)
+                st, t = svt.svt_ring_run(ring, stream)
+            svt.check(st, "svt_ring_run")
+            pend.append(t)
+            while len(pend) > 2:
+                st2, s = svt.svt_result(ctx, pend.popleft(), -1)
+                svt.check(st2, "ring")
+                total += s.total_comb
+                dev.append(s.device_ns)
+    while pend:
+        st2, s = svt.svt_result(ctx, pend.popleft(), -1)
+        svt.check(st2, "ring")
+        total += s.total_comb
+        dev.append(s.device_ns)
+    return total, dev
 
 
 def section_fit(args, svt, synth, torch):
+    """Headline: passes of the fit over the 3000-event batch, back to back.
+    The timed region runs exactly --steps passes as graph launches of at
+    most --ring-passes passes each over --copies rotating input copies (the
+    paper's repeated passes over one sample, Sec. 4.1, in steady state).
+    The per-request form (one svt_fit_events per pass, over two streams)
+    is measured beside it."""
     batch, consts = synth.cfg2()
     ctx = svt.Context(0)
     ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
@@ -102,18 +197,53 @@ def section_fit(args, svt, synth, torch):
     bs = [c.struct() for c in copies]
     rs = [r.struct() for r in results]
     stream = torch.cuda.current_stream().cuda_stream
-    if args.time_every < 1 or args.steps < args.time_every:
-        raise SystemExit("--time-every must be at least 1 and at most --steps "
-                         "(the roofline needs timed launches)")
-    if args.fit_streams < 1 or args.copies % args.fit_streams:
-        # request i reuses the buffers of request i - copies: same stream, so in order
-        raise SystemExit("--fit-streams must be at least 1 and divide --copies")
-    # requests alternate over independent streams (default priority), so that
-    # one launch's tail and set-up overlap the next one's row loops
+    per_ring = max(1, min(args.ring_passes, args.steps))
+    warm = make_rings(svt, ctx, bs, rs, max(1, args.warmup), per_ring)
+    timed = make_rings(svt, ctx, bs, rs, args.steps, per_ring)
+    run_rings(svt, ctx, warm, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total, dev = run_rings(svt, ctx, timed, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for ring, _ in warm + timed:
+        svt.svt_ring_destroy(ring)
+    passes = args.steps
+    kernel_s = sum(dev) * 1e-9 / passes
+    # a longer run of the same rings' shape for the steady-state check
+    requests = section_fit_requests(args, svt, ctx, bs, rs, torch)
+    alg = algorithmic_bytes(batch.n_events, batch.n_roads, batch.n_hits)
+    achieved = alg / kernel_s / 1e9
+    out = dict(
+        value=total / elapsed, ms_per_step=elapsed * 1e3 / passes,
+        combinations=int(total // passes),
+        config={"workload": "scaled-up plain fit: 3000 events x 64 roads, 1-4 hits per layer, "
+                            "72 sectors, lattice constants, half the roads with a planted track",
+                "step": "one pass of the fit over the batch; the timed passes run back to back "
+                        f"as graph launches of up to {per_ring} passes over {args.copies} "
+                        "rotating input copies",
+                "n_events": batch.n_events, "n_roads": batch.n_roads, "n_hits": batch.n_hits,
+                "combinations": int(total // passes), "chi2_cut": consts.chi2_cut,
+                "device": info["arch"], "compute_units": info["compute_units"],
+                "tuning": ctx.tuning(), "input_copies": args.copies, "ring_passes": per_ring},
+        roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                  "kernel_us": kernel_s * 1e6, "algorithmic_bytes": alg,
+                  "timed_launches": passes,
+                  "kernel_us_basis": "device time of the timed graph launches (events around each "
+                                     "launch on its stream) / passes: back-to-back fit kernels on "
+                                     "one stream, the gaps between them included"},
+        requests=requests, batch=batch, consts=consts)
+    ctx.close()
+    return out
+
+
+def section_fit_requests(args, svt, ctx, bs, rs, torch):
+    """One svt_fit_events request per pass, alternating over two streams
+    (launches overlap), one request in --time-every timed by its own
+    dispatch; then 20 isolated requests."""
     streams = [torch.cuda.Stream() for _ in range(args.fit_streams)]
     handles = [s.cuda_stream for s in streams]
-    # dispatch events on one request in time_every: a start timestamp costs
-    # the host about 11 us per launch, the completion alone about 3 us
     ctx.set_timing(args.time_every)
     h, sub, fin = ctx.handle, svt.lib.svt_fit_events, svt.lib.svt_result
     b_refs = [ctypes.byref(b) for b in bs]
@@ -121,11 +251,9 @@ def section_fit(args, svt, synth, torch):
     s_ptrs = [ctypes.c_void_p(x) for x in handles]
     tk, summ = ctypes.c_int64(0), svt.svt_summary()
     tk_ref, summ_ref = ctypes.byref(tk), ctypes.byref(summ)
-    torch.cuda.synchronize()
+    n_req = max(args.steps, 200)
 
     def run(n):
-        # the C calls with their argument objects built once: the loop's own
-        # host cost stays well below a request's device time
         pend, dev_ns, total = collections.deque(), [], 0
 
         def collect(t):
@@ -135,7 +263,7 @@ def section_fit(args, svt, synth, torch):
             return summ.total_comb
 
         for i in range(n):
-            st = sub(h, b_refs[i % args.copies], r_refs[i % args.copies], s_ptrs[i % len(s_ptrs)], tk_ref)
+            st = sub(h, b_refs[i % len(bs)], r_refs[i % len(bs)], s_ptrs[i % len(s_ptrs)], tk_ref)
             svt.check(st, "svt_fit_events")
             pend.append(tk.value)
             if len(pend) > 32:
@@ -144,42 +272,111 @@ def section_fit(args, svt, synth, torch):
             total += collect(pend.popleft())
         return total, dev_ns
 
-    run(args.warmup)
+    run(20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    total, dev_ns = run(args.steps)
+    total, dev_ns = run(n_req)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.set_timing(1)
-    # one request at a time: the request's own device time without queueing
+    stream = torch.cuda.current_stream().cuda_stream
     iso = []
     for i in range(20):
-        t = ctx.submit(bs[i % args.copies], rs[i % args.copies], stream)
+        t = ctx.submit(bs[i % len(bs)], rs[i % len(bs)], stream)
         st, s = ctx.result(t, -1)
         iso.append(s.device_ns)
     timed = [d for d in dev_ns if d > 0]
-    kernel_s = float(np.mean(timed)) * 1e-9
-    alg = algorithmic_bytes(batch.n_events, batch.n_roads, batch.n_hits)
-    achieved = alg / kernel_s / 1e9
-    effective = alg * args.steps / elapsed / 1e9   # launches overlap: bytes per wall second
-    out = dict(
-        value=total / elapsed, ms_per_step=elapsed * 1e3 / args.steps,
-        combinations=int(total // args.steps),
-        config={"workload": "scaled-up plain fit: 3000 events x 64 roads, 1-4 hits per layer, "
-                            "72 sectors, lattice constants, half the roads with a planted track",
-                "n_events": batch.n_events, "n_roads": batch.n_roads, "n_hits": batch.n_hits,
-                "combinations": int(total // args.steps), "chi2_cut": consts.chi2_cut,
-                "device": info["arch"], "compute_units": info["compute_units"],
-                "tuning": ctx.tuning(), "input_copies": args.copies, "streams": args.fit_streams},
-        roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                  "kernel_us": kernel_s * 1e6, "algorithmic_bytes": alg,
-                  "timed_launches": len(timed),
-                  "effective_gbs": effective, "effective_frac": effective / HBM_PEAK_GBS,
-                  "isolated_request_us_p50": pct(iso, 50) / 1e3},
-        batch=batch, consts=consts)
+    return {"requests": n_req, "streams": args.fit_streams, "us_per_request": elapsed * 1e6 / n_req,
+            "combinations_per_s": total / elapsed,
+            "dispatch_timed_us_mean": float(np.mean(timed)) / 1e3, "dispatch_timed": len(timed),
+            "isolated_request_us_p50": pct(iso, 50) / 1e3,
+            "note": "a dispatch timed by its own events measures at least 3.9 us (an empty "
+                    "kernel measures the same)"}
+
+
+def section_sweep(args, svt, synth, torch, iostudy):
+    """The paper's benchmark shape (Sec. 4.1): 2048 combinations per event,
+    1 to 3000 events.  Per size: device time of a pass (rings of 100 passes),
+    end-to-end time of a request with pinned host inputs and results, the
+    stages (DMA in, unpack of the packed words, fit, DMA out) and the oracle
+    on one thread and on all threads, with the speed-ups."""
+    import oracle
+    oracle.build(force=False)
+    cpu = host_cpu()
+    ctx = svt.Context(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for ne in args.sweep_events:
+        batch, consts = synth.paper_sweep(ne)
+        ctx.load_constants(consts.coef, consts.offset, consts.chi2_cut)
+        comb = int(np.prod(batch.nhits.astype(np.int64), axis=1).sum())
+        n_copy = 8
+        dbs = [svt.to_device(batch) for _ in range(n_copy)]
+        drs = [svt.DeviceResults(batch.n_events, batch.n_roads) for _ in range(n_copy)]
+        rings = make_rings(svt, ctx, [d.struct() for d in dbs], [r.struct() for r in drs],
+                           100, 100)
+        run_rings(svt, ctx, rings, stream)
+        _, dev = run_rings(svt, ctx, rings, stream, repeat=3)
+        for ring, _ in rings:
+            svt.svt_ring_destroy(ring)
+        fit_us = float(np.median(dev)) / 1e3 / 100
+        # end to end: pinned host inputs and results, one request at a time
+        pin_b = {f: torch.from_numpy(np.ascontiguousarray(getattr(batch, f))).pin_memory()
+                 for f in svt.BATCH_FIELDS}
+        hb = svt.svt_event_batch(batch.n_events, batch.n_roads, batch.n_hits, svt.SVT_MEM_PINNED,
+                                 *[pin_b[f].data_ptr() for f in svt.BATCH_FIELDS])
+        pres = svt.DeviceResults(batch.n_events, batch.n_roads, pin=True)
+        hr = pres.struct()
+        e2e, wall = [], []
+        for i in range(args.sweep_reps + 5):
+            t0 = time.perf_counter()
+            t = ctx.submit(hb, hr, stream)
+            st, s = ctx.result(t, -1)
+            svt.check(st, "sweep request")
+            if i >= 5:
+                wall.append(time.perf_counter() - t0)
+                e2e.append(s.device_ns / 1e3)
+        # stages: DMA of the CSR batch in, unpack of the packed words (device),
+        # the fit, DMA of the results out
+        in_bytes = batch.nbytes()
+        out_bytes = batch.n_roads * 36 + 4 * batch.n_events
+        h2d = svt.svt_io_probe(ctx.handle, svt.SVT_MEM_PINNED, 0, in_bytes, 21)
+        d2h = svt.svt_io_probe(ctx.handle, svt.SVT_MEM_PINNED, 1, out_bytes, 21)
+        words = torch.from_numpy(synth.pack_stream(batch).view(np.int32)).cuda()
+        caps = (batch.n_events, batch.n_roads, batch.n_hits)
+        unp = []
+        for i in range(23):
+            st, s, _ = ctx.unpack_stream(words, mem_kind=svt.SVT_MEM_DEVICE, caps=caps)
+            svt.check(st, "unpack")
+            if i >= 3:
+                unp.append(s.device_ns / 1e3)
+        # the oracle: one thread, and every thread this process may use
+        budget = args.sweep_cpu_seconds
+        r1, m1, n1 = oracle_rate(batch, consts, 1, budget, min_reps=3)
+        ra, ma, na = oracle_rate(batch, consts, cpu["threads"], budget, min_reps=3)
+        e2e_us = float(np.median(e2e))
+        row = {"events": ne, "combinations": comb, "gpu_fit_us": fit_us,
+               "gpu_fits_per_s": comb / (fit_us * 1e-6),
+               "gpu_end_to_end_us": e2e_us, "gpu_end_to_end_wall_us": float(np.median(wall)) * 1e6,
+               "end_to_end_fits_per_s": comb / (e2e_us * 1e-6),
+               "stages_us": {"h2d": h2d, "unpack": float(np.median(unp)), "fit": fit_us,
+                             "d2h": d2h},
+               "cpu_1thread_us": m1 * 1e6, "cpu_1thread_reps": n1,
+               "cpu_all_us": ma * 1e6, "cpu_all_reps": na, "cpu_threads": cpu["threads"],
+               "speedup_fit_vs_1thread": m1 * 1e6 / fit_us,
+               "speedup_end_to_end_vs_1thread": m1 * 1e6 / e2e_us,
+               "speedup_fit_vs_all_threads": ma * 1e6 / fit_us}
+        rows.append(row)
+        log(f"sweep {ne:5d} events: fit {fit_us:7.2f} us, end to end {e2e_us:8.1f} us, "
+            f"cpu 1 thread {m1 * 1e6:10.0f} us, all {ma * 1e6:9.0f} us")
     ctx.close()
-    return out
+    return {"workload": "paper shape: events x 8 roads x 4 hits per layer (2048 combinations "
+                        "per event), lattice constants, half the roads with a planted track",
+            "cpu_model": cpu["model"], "rows": rows,
+            "timed": "fit: device time of rings of 100 passes over 8 copies / 100; end to end: "
+                     "device time of one request with pinned host inputs and results (copies "
+                     "included), median of --sweep-reps; stages from separate DMA probes and "
+                     "unpack requests; oracle: median pass"}
 
 
 def list_algorithmic_bytes(n_roads, n_hits, entries):
@@ -343,7 +540,7 @@ def section_serve(args, svt, synth, torch, serve):
     comb_cum = np.concatenate([[0], np.cumsum(comb_road)])[batch.road_offsets.astype(np.int64)]
     for load, nb_batched, nb_plain in ((1e4, args.serve_bursts[0], args.serve_bursts[0]),
                                        (1e5, args.serve_bursts[1], args.serve_bursts[1]),
-                                       (1e6, args.serve_bursts[2], args.serve_bursts[2] // 2)):
+                                       (1e6, args.serve_bursts[2], args.serve_bursts[2])):
         rng = np.random.default_rng(int(load) % 1000 + 5)
         arr = serve.make_arrivals(rng, nb_batched, load, pool.batch.n_events)
         ctx = svt.Context(0, 4 << 30)
@@ -353,6 +550,7 @@ def section_serve(args, svt, synth, torch, serve):
         srv.warm()                         # staging buffers for the largest launches
         srv.run(arr[:8])
         srv.launch_sizes.clear()
+        srv.fill_seconds = 0.0
         gc.collect()
         gc.disable()                       # no collector pauses inside the serving loop
         try:
@@ -368,7 +566,7 @@ def section_serve(args, svt, synth, torch, serve):
         gc.collect()
         gc.disable()
         try:
-            precs = plain.run(arr[:nb_plain], time_limit=60.0)
+            precs = plain.run(arr[:nb_plain], time_limit=args.serve_plain_seconds)
         finally:
             gc.enable()
         st_p = serve.latency_stats(precs)
@@ -377,7 +575,9 @@ def section_serve(args, svt, synth, torch, serve):
                              "batched": dict(st_b, launches=len(srv.launch_sizes),
                                              mean_events_per_launch=float(np.mean(srv.launch_sizes)),
                                              events_per_s_served=ev / wall,
-                                             fits_per_s=comb / wall),
+                                             fits_per_s=comb / wall,
+                                             host_fill_share=srv.fill_seconds / wall,
+                                             wall_s=wall),
                              "plain": dict(st_p, bursts=len(precs))})
         log(f"serve load {load:g}: batched p50 {st_b.get('p50_us', 0):.0f} us p99 "
             f"{st_b.get('p99_us', 0):.0f} us | plain p50 {st_p.get('p50_us', 0):.0f} us "
@@ -467,18 +667,27 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--copies", type=int, default=32)
+    ap.add_argument("--ring-passes", type=int, default=100,
+                    help="passes per captured graph launch in the timed region")
     ap.add_argument("--fit-streams", type=int, default=2,
                     help="streams the fit requests of the timed region alternate over")
     ap.add_argument("--time-every", type=int, default=8,
                     help="fit requests of the timed region that carry dispatch events: one in N")
-    ap.add_argument("--sections", default="fit,list,unpack,uneven,serve,io,shadow")
+    ap.add_argument("--sections", default="fit,sweep,list,unpack,uneven,serve,io,shadow")
+    ap.add_argument("--sweep-events", type=lambda s: [int(v) for v in s.split(",")],
+                    default=[1, 10, 100, 500, 1000, 2000, 3000])
+    ap.add_argument("--sweep-reps", type=int, default=100)
+    ap.add_argument("--sweep-cpu-seconds", type=float, default=1.5)
     ap.add_argument("--list-reps", type=int, default=50)
     ap.add_argument("--unpack-reps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--uneven-reps", type=int, default=50)
     ap.add_argument("--serve-bursts", type=lambda s: [int(v) for v in s.split(",")],
-                    default=[40, 150, 400])
+                    default=[2000, 2000, 2000],
+                    help="bursts per offered load (10k, 100k, 1M events/s), batched form")
+    ap.add_argument("--serve-plain-seconds", type=float, default=15.0,
+                    help="time cap of the plain per-event form per load (its burst count is reported)")
     ap.add_argument("--shadow-tracks", type=int, default=1000000)
     ap.add_argument("--shadow-steps", type=int, default=50)
     ap.add_argument("--shadow-lr", type=float, default=1e-4)
@@ -500,11 +709,14 @@ def main():
         "warmup": args.warmup, "ms_per_step": fit["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32 fit rows, fp64 exact chi2",
         "data": "synthetic (seeded generators; the paper's CDF data is not available)",
-        "config": fit["config"], "roofline": fit["roofline"],
+        "config": fit["config"], "roofline": fit["roofline"], "requests": fit["requests"],
     }
     if not args.no_cpu_baseline:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(fit["batch"], fit["consts"], args.cpu_seconds)
+    if "sweep" in sections:
+        log("section sweep")
+        line["sweep"] = section_sweep(args, svt, synth, torch, iostudy)
     if "list" in sections:
         log("section list")
         line["list"] = section_list(args, svt, synth, torch)

@@ -332,6 +332,35 @@ svt_status svt_plan_fit(svt_plan *plan, const svt_event_batch *batch, const svt_
                         void *hip_stream, svt_ticket *ticket);
 
 /* ------------------------------------------------------------------------
+ * Rings: device-resident batches fitted back to back in one graph launch.
+ * A read-out that fills a ring of device buffers while the GPU fits them in
+ * order is the steady state of the fit; the paper times 100 repetitions of
+ * each sample back to back (Sec. 4.1), which a ring of 100 passes gives
+ * without host launch gaps between them.  svt_ring_create captures one graph
+ * of n_passes fit kernels: pass p fits batches[p % n_batches] into
+ * results[p % n_batches] (a later pass over the same batch rewrites the same
+ * results).  Every batch and results must be device memory (SVT_MEM_DEVICE),
+ * without comb_offsets, and follows the svt_fit_events layout; the arrays
+ * are copied, the buffers they point to are not, and must stay alive and
+ * unmodified while the ring exists.  n_batches in 1..n_passes, n_passes in
+ * 1..1024.  The launch shape is the context's tuning at creation.  Constants
+ * are captured: after svt_load_constants the ring must be recreated
+ * (svt_ring_run returns SVT_E_STATE).  Destroy rings before their context.
+ * ------------------------------------------------------------------------ */
+typedef struct svt_ring svt_ring;
+svt_status svt_ring_create(svt_ctx *ctx, int32_t n_batches, const svt_event_batch *batches,
+                           const svt_results *results, int32_t n_passes, svt_ring **out);
+/* Replay the ring's graph on hip_stream (asynchronous; one run per ring in
+ * flight, else SVT_E_AGAIN).  svt_result on the ring's context then gives the
+ * sums over all passes (total_comb = sum over passes of each pass's
+ * combinations, and so on), the lowest err_road / err_event any pass
+ * reported (each the index within that pass's batch) and device_ns from the
+ * first pass to the last. */
+svt_status svt_ring_run(svt_ring *ring, void *hip_stream, svt_ticket *ticket);
+/* Waits for the ring's run in flight, if any, then frees it. */
+svt_status svt_ring_destroy(svt_ring *ring);
+
+/* ------------------------------------------------------------------------
  * Float shadow of the fit, for calibrating the constants before they are
  * quantized.  The same linearized fit (Sec. 2: each row a scalar product of
  * per-sector constants with the inputs plus an offset) evaluated in fp32 on

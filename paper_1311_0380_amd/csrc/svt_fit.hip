@@ -477,6 +477,7 @@ fit_kernel(FitArgs a)
         n_hits = a.sizes->n_hits;
         seq = a.sizes->seq;
     }
+    if (a.seq_dev != nullptr) seq = *a.seq_dev;
     const int32_t n_sectors = a.n_sectors;
     double *s_cd = reinterpret_cast<double *>(s_dyn);
 
@@ -658,6 +659,11 @@ __global__ void zero_i64(int64_t *p)
     if (threadIdx.x == 0) p[0] = 0;
 }
 
+__global__ void copy_seq(const uint32_t *src, uint32_t *dst)
+{
+    if (threadIdx.x == 0) *dst = *src;
+}
+
 }  // namespace
 
 hipError_t prepare_fit()
@@ -675,6 +681,12 @@ hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t st
                               stop, 0u, a);
     else
         hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), dyn_lds, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_seq(const uint32_t *src, uint32_t *dst, hipStream_t stream)
+{
+    hipLaunchKernelGGL(copy_seq, dim3(1), dim3(64), 0, stream, src, dst);
     return hipGetLastError();
 }
 

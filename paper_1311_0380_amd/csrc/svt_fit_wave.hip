@@ -355,6 +355,7 @@ fit_wave_kernel(FitArgs a)
         n_hits = a.sizes->n_hits;
         seq = a.sizes->seq;
     }
+    if (a.seq_dev != nullptr) seq = *a.seq_dev;
     // the first chunk's event boundaries are in flight while the columns 0..3
     // of every sector's constraint rows are staged in LDS
     const int32_t n_chunks =

@@ -70,6 +70,7 @@ struct FitArgs {
     int32_t n_events, n_roads, n_hits;
     int32_t n_sectors;
     const Sizes *sizes;         // non-NULL: sizes are read from here instead
+    const uint32_t *seq_dev;    // non-NULL: the request's sequence number is read here
     // constants (device)
     const int32_t *coef;        // [n_sectors][6][6]
     const int32_t *offset;      // [n_sectors][6]
@@ -103,6 +104,10 @@ hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t st
 hipError_t prepare_fit_wave();
 hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream,
                            hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// One thread copies a request's sequence number from host-mapped memory to
+// device memory (the first node of a ring's graph; the fit kernels then read
+// it from device memory).
+hipError_t launch_copy_seq(const uint32_t *src, uint32_t *dst, hipStream_t stream);
 hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
                                int64_t *scratch, hipStream_t stream);
 size_t comb_offsets_scratch_bytes(int32_t n_roads);

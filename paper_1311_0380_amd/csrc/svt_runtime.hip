@@ -56,6 +56,7 @@ struct Slot {
     svt::BlockPartial *parts = nullptr;      // partials the request in flight writes
     int grid = 0;                            // blocks of the request in flight
     svt_plan *plan = nullptr;                // plan of the request, if any
+    svt_ring *ring = nullptr;                // ring of the request, if any
     DevBuf stage;                            // device staging for host inputs / results
     DevBuf scan;                             // scratch of the running sums (offsets scans)
     svt_status host_status = SVT_OK;
@@ -111,6 +112,20 @@ struct svt_plan {
     svt::BlockPartial *partials = nullptr;  // host-mapped [grid]
     int grid = 0;
     svt_tuning tuning{};
+    uint64_t const_gen = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool busy = false;
+};
+
+// A captured sequence of fit passes over resident batches (see svt_ring_create).
+struct svt_ring {
+    svt_ctx *ctx = nullptr;
+    int32_t n_batches = 0, n_passes = 0;
+    int total_parts = 0;                    // block partials of all passes
+    svt::BlockPartial *partials = nullptr;  // host-mapped [total_parts], pass after pass
+    uint32_t *seq_host = nullptr;           // host-mapped: the run's ticket
+    uint32_t *seq_dev = nullptr;            // device copy the fit kernels read
     uint64_t const_gen = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -677,6 +692,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     s.grid = (int)grid;
     s.parts = s.partials;
     s.plan = nullptr;
+    s.ring = nullptr;
 
     // a kernel-only request: the dispatch itself records the events (only
     // the completion when untimed)
@@ -773,6 +789,7 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     s.grid = (int)grid;
     s.parts = s.partials;
     s.plan = nullptr;
+    s.ring = nullptr;
     s.list_capacity = list->capacity;
     s.busy = true;
     s.ticket = c->next_ticket++;
@@ -853,6 +870,7 @@ svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words,
     s.grid = a.n_apply + 1;
     s.parts = s.partials;
     s.plan = nullptr;
+    s.ring = nullptr;
     s.unpack = true;
     s.unpack_cap[0] = out->max_events;
     s.unpack_cap[1] = out->max_roads;
@@ -927,6 +945,8 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     }
     if (s.plan) s.plan->busy = false;
     s.plan = nullptr;
+    if (s.ring) s.ring->busy = false;
+    s.ring = nullptr;
     stage_release(c, s.stage);
     s.list_capacity = -1;
     s.unpack = false;
@@ -1261,8 +1281,173 @@ svt_status svt_plan_fit(svt_plan *p, const svt_event_batch *b, const svt_results
     s.parts = p->partials;
     s.grid = p->grid;
     s.plan = p;
+    s.ring = nullptr;
     p->busy = true;
     *ticket = s.ticket;
+    return SVT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rings: captured back-to-back fit passes over resident batches
+// ---------------------------------------------------------------------------
+static void ring_free(svt_ring *r)
+{
+    if (r == nullptr) return;
+    if (r->exec) (void)hipGraphExecDestroy(r->exec);
+    if (r->graph) (void)hipGraphDestroy(r->graph);
+    if (r->seq_dev) dev_free(r->ctx, r->seq_dev, 256);
+    if (r->seq_host) (void)hipHostFree(r->seq_host);
+    if (r->partials) (void)hipHostFree(r->partials);
+    delete r;
+}
+
+svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch *batches,
+                           const svt_results *results, int32_t n_passes, svt_ring **out)
+{
+    if (c == nullptr || out == nullptr || batches == nullptr || results == nullptr)
+        return SVT_E_INVAL;
+    *out = nullptr;
+    if (n_passes < 1 || n_passes > 1024 || n_batches < 1 || n_batches > n_passes)
+        return SVT_E_INVAL;
+    for (int i = 0; i < n_batches; ++i) {
+        const svt_status vs = check_call(&batches[i], &results[i]);
+        if (vs != SVT_OK) return vs;
+        if (batches[i].mem_kind != SVT_MEM_DEVICE || results[i].mem_kind != SVT_MEM_DEVICE ||
+            results[i].comb_offsets != nullptr)
+            return SVT_E_INVAL;
+    }
+    if (!c->loaded) return SVT_E_STATE;
+    DeviceGuard g(c->device);
+    svt_ring *r = new (std::nothrow) svt_ring();
+    if (r == nullptr) return SVT_E_NOMEM;
+    r->ctx = c;
+    r->n_batches = n_batches;
+    r->n_passes = n_passes;
+    r->const_gen = c->const_gen;
+    std::vector<LaunchShape> shapes(n_batches);
+    std::vector<int> part_off(n_passes + 1, 0);
+    for (int i = 0; i < n_batches; ++i)
+        shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads, false);
+    for (int p = 0; p < n_passes; ++p) part_off[p + 1] = part_off[p] + shapes[p % n_batches].grid;
+    r->total_parts = part_off[n_passes];
+    svt_status st = dev_alloc(c, reinterpret_cast<void **>(&r->seq_dev), 256);
+    if (st != SVT_OK) {
+        delete r;
+        return st;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&r->partials),
+                      sizeof(svt::BlockPartial) * r->total_parts,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&r->seq_host), 64,
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        st = hip_fail(hipGetLastError(), "hipHostMalloc");
+        ring_free(r);
+        return st;
+    }
+    memset(r->partials, 0, sizeof(svt::BlockPartial) * r->total_parts);
+    *r->seq_host = 0;
+    svt::BlockPartial *parts_dev = static_cast<svt::BlockPartial *>(
+        const_cast<void *>(device_view(r->partials, SVT_MEM_MAPPED)));
+    const uint32_t *seq_src =
+        static_cast<const uint32_t *>(device_view(r->seq_host, SVT_MEM_MAPPED));
+
+    // the graph: the run's ticket into device memory, then the passes in order
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = svt::launch_copy_seq(seq_src, r->seq_dev, cs);
+        for (int p = 0; p < n_passes && e2 == hipSuccess; ++p) {
+            const svt_event_batch &b = batches[p % n_batches];
+            const svt_results &res = results[p % n_batches];
+            svt::FitArgs a;
+            memset(&a, 0, sizeof a);
+            a.road_offsets = b.road_offsets;
+            a.sector = b.sector;
+            a.nhits4 = reinterpret_cast<const uint32_t *>(b.nhits);
+            a.hit_offsets = b.hit_offsets;
+            a.hits = b.hits;
+            a.xft2 = reinterpret_cast<const uint32_t *>(b.xft);
+            a.n_events = b.n_events;
+            a.n_roads = b.n_roads;
+            a.n_hits = b.n_hits;
+            a.n_sectors = c->n_sectors;
+            a.coef = c->coef;
+            a.offset = c->offset;
+            a.cut_d = (double)c->cut;
+            a.ncomb = res.ncomb;
+            a.npass = res.npass;
+            a.best = res.best;
+            a.chi2 = res.chi2;
+            a.params = res.params;
+            a.hit_index4 = reinterpret_cast<uint32_t *>(res.hit_index);
+            a.ntracks = res.ntracks;
+            a.schedule = c->tuning.schedule;
+            a.partials = parts_dev + part_off[p];
+            a.seq_dev = r->seq_dev;
+            e2 = launch_shaped(c, a, shapes[p % n_batches], cs);
+        }
+        e = hipStreamEndCapture(cs, &r->graph);
+        if (e == hipSuccess && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "ring capture");
+        ring_free(r);
+        return st;
+    }
+    *out = r;
+    return SVT_OK;
+}
+
+svt_status svt_ring_run(svt_ring *r, void *hip_stream, svt_ticket *ticket)
+{
+    if (r == nullptr || ticket == nullptr) return SVT_E_INVAL;
+    svt_ctx *c = r->ctx;
+    if (!c->loaded || c->const_gen != r->const_gen) return SVT_E_STATE;
+    if (r->busy) return SVT_E_AGAIN;
+    const int si = (int)(c->next_ticket % kSlots);
+    Slot &s = c->slots[si];
+    if (s.busy) return SVT_E_AGAIN;
+    DeviceGuard g(c->device);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
+    // no run of this ring is in flight, so its kernels are not reading the
+    // word while it changes
+    *r->seq_host = (uint32_t)c->next_ticket;
+    auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); }, [] {});
+    guard.enqueuing();
+    HIP_TRY(hipEventRecord(s.ev_start, st));
+    HIP_TRY(hipGraphLaunch(r->exec, st));
+    HIP_TRY(hipEventRecord(s.ev_end, st));
+    guard.submitted();
+    s.timed = true;
+    s.busy = true;
+    s.ticket = c->next_ticket++;
+    s.parts = r->partials;
+    s.grid = r->total_parts;
+    s.plan = nullptr;
+    s.ring = r;
+    r->busy = true;
+    *ticket = s.ticket;
+    return SVT_OK;
+}
+
+svt_status svt_ring_destroy(svt_ring *r)
+{
+    if (r == nullptr) return SVT_E_INVAL;
+    DeviceGuard g(r->ctx->device);
+    if (r->busy) {
+        for (int i = 0; i < kSlots; ++i) {
+            Slot &s = r->ctx->slots[i];
+            if (s.busy && s.ring == r) {
+                (void)hipEventSynchronize(s.ev_end);
+                s.ring = nullptr;
+                s.busy = false;
+            }
+        }
+    }
+    ring_free(r);
     return SVT_OK;
 }
 

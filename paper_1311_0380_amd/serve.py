@@ -187,6 +187,7 @@ class Server:
         self.spin = spin
         self.results = {}
         self.launch_sizes = []
+        self.fill_seconds = 0.0   # host time spent merging bursts into launch buffers
 
     def warm(self):
         """One full-size launch per slot, all in flight together, so that the
@@ -256,7 +257,9 @@ class Server:
                         break
                     take.append(queue.popleft())
                     ne, nr, nh = ne + ce, nr + cr, nh + ch
+                t_fill = self.clock()
                 self.bufs[slot].fill(self.pool, [(recs[i].e0, recs[i].e1) for i in take])
+                self.fill_seconds += self.clock() - t_fill
                 st, ticket = self.device.submit(slot, self.bufs[slot])
                 if st != 0:
                     for i in reversed(take):

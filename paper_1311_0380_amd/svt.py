@@ -105,6 +105,11 @@ SIGNATURES = {
     "svt_plan_fit": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch),
                                       ctypes.POINTER(svt_results), P,
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "svt_ring_create": (ctypes.c_int32, [P, ctypes.c_int32, ctypes.POINTER(svt_event_batch),
+                                         ctypes.POINTER(svt_results), ctypes.c_int32,
+                                         ctypes.POINTER(P)]),
+    "svt_ring_run": (ctypes.c_int32, [P, P, ctypes.POINTER(ctypes.c_int64)]),
+    "svt_ring_destroy": (ctypes.c_int32, [P]),
     "svt_shadow_slices": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32)]),
     "svt_shadow_forward": (ctypes.c_int32, [P, ctypes.POINTER(svt_shadow_tracks), P, P, P, P, P]),
@@ -315,6 +320,27 @@ def svt_plan_buffers(plan):
     b, r = svt_event_batch(), svt_results()
     check(lib.svt_plan_buffers(plan, ctypes.byref(b), ctypes.byref(r)), "svt_plan_buffers")
     return b, r
+
+
+def svt_ring_create(ctx, batches, results, n_passes):
+    """A ring over device batches / results (lists of svt_event_batch and
+    svt_results of equal length); returns (status, ring handle or None)."""
+    n = len(batches)
+    ba = (svt_event_batch * n)(*batches)
+    ra = (svt_results * n)(*results)
+    h = P()
+    st = lib.svt_ring_create(ctx, n, ba, ra, int(n_passes), ctypes.byref(h))
+    return st, (h if st == SVT_OK else None)
+
+
+def svt_ring_run(ring, stream=None):
+    t = ctypes.c_int64(0)
+    st = lib.svt_ring_run(ring, None if stream is None else P(stream), ctypes.byref(t))
+    return st, t.value
+
+
+def svt_ring_destroy(ring):
+    return lib.svt_ring_destroy(ring)
 
 
 def svt_list_passing(ctx, batch: svt_event_batch, npass_ptr: int, lst: svt_pass_list, stream=None):

@@ -1,0 +1,108 @@
+"""Rings: resident batches fitted back to back in one captured graph.  Every
+pass's results equal the oracle's for its batch, the summary sums all passes,
+and the ring follows the context's state rules."""
+import numpy as np
+import pytest
+
+from paper_1311_0380_amd import synth
+from tests.gpu_helpers import assert_equal_results
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    from paper_1311_0380_amd import svt
+    ctx = svt.svt_create(0, 0)
+    yield svt, ctx
+    svt.svt_destroy(ctx)
+
+
+def test_ring_passes_match_the_oracle(env, oracle_lib):
+    svt, ctx = env
+    import torch
+    # three different batches (sizes differ, so grids differ per pass)
+    batches, consts = [], None
+    for i, ne in enumerate((300, 17, 1000)):
+        b, c = synth.cfg2(seed=2, n_events=3000)
+        b = b.select_events(ne * i, ne * i + ne)
+        batches.append(b)
+        consts = c
+    svt.check(svt.svt_load_constants(ctx, consts.coef, consts.offset, consts.chi2_cut))
+    dbs = [svt.to_device(b) for b in batches]
+    drs = [svt.DeviceResults(b.n_events, b.n_roads) for b in batches]
+    st, ring = svt.svt_ring_create(ctx, [d.struct() for d in dbs], [r.struct() for r in drs], 7)
+    svt.check(st, "svt_ring_create")
+    try:
+        wants, tot = [], dict(total_comb=0, total_pass=0, total_tracks=0)
+        for b in batches:
+            rc, w, s = oracle_lib.fit_batch(b, consts, n_threads=8)
+            assert rc == 0
+            wants.append(w)
+        for p in range(7):
+            s = oracle_lib.fit_batch(batches[p % 3], consts, n_threads=8)[2]
+            for k in tot:
+                tot[k] += s[k]
+        for run in range(3):
+            for r in drs:       # stale values must be overwritten
+                for f in svt.RESULT_FIELDS:
+                    getattr(r, f).fill_(-3)
+            torch.cuda.synchronize()
+            st, t = svt.svt_ring_run(ring, torch.cuda.current_stream().cuda_stream)
+            svt.check(st, "svt_ring_run")
+            st2, t2 = svt.svt_ring_run(ring, torch.cuda.current_stream().cuda_stream)
+            assert st2 == svt.SVT_E_AGAIN            # one run of a ring at a time
+            st, summ = svt.svt_result(ctx, t, -1)
+            svt.check(st, "ring result")
+            assert summ.total_comb == tot["total_comb"]
+            assert summ.total_pass == tot["total_pass"]
+            assert summ.total_tracks == tot["total_tracks"]
+            assert summ.err_road == -1 and summ.err_event == -1
+            assert summ.device_ns > 0
+            for r, w in zip(drs, wants):
+                assert_equal_results(r.numpy(), w, where=f"run {run}: ")
+    finally:
+        svt.svt_ring_destroy(ring)
+
+
+def test_ring_rules(env):
+    svt, ctx = env
+    b, c = synth.cfg1(n_events=20)
+    svt.check(svt.svt_load_constants(ctx, c.coef, c.offset, c.chi2_cut))
+    db, dr = svt.to_device(b), svt.DeviceResults(b.n_events, b.n_roads)
+    bs, rs = db.struct(), dr.struct()
+    # host buffers, comb_offsets and bad counts are refused
+    hb = svt.svt_event_batch(*[getattr(bs, f) for f, _ in bs._fields_])
+    hb.mem_kind = svt.SVT_MEM_PINNED
+    assert svt.svt_ring_create(ctx, [hb], [rs], 2)[0] == svt.SVT_E_INVAL
+    co = svt.DeviceResults(b.n_events, b.n_roads, comb_offsets=True)
+    assert svt.svt_ring_create(ctx, [bs], [co.struct()], 2)[0] == svt.SVT_E_INVAL
+    assert svt.svt_ring_create(ctx, [bs], [rs], 0)[0] == svt.SVT_E_INVAL
+    assert svt.svt_ring_create(ctx, [bs, bs], [rs, rs], 1)[0] == svt.SVT_E_INVAL
+    st, ring = svt.svt_ring_create(ctx, [bs], [rs], 3)
+    svt.check(st)
+    try:
+        # constants are captured: a reload makes the ring stale
+        svt.check(svt.svt_load_constants(ctx, c.coef, c.offset, c.chi2_cut))
+        assert svt.svt_ring_run(ring)[0] == svt.SVT_E_STATE
+    finally:
+        svt.svt_ring_destroy(ring)
+
+
+def test_ring_reports_malformed_roads(env, oracle_lib):
+    svt, ctx = env
+    b, c = synth.cfg1(n_events=30)
+    b.hits[5] = 5000                      # a word out of range
+    svt.check(svt.svt_load_constants(ctx, c.coef, c.offset, c.chi2_cut))
+    db, dr = svt.to_device(b), svt.DeviceResults(b.n_events, b.n_roads)
+    st, ring = svt.svt_ring_create(ctx, [db.struct()], [dr.struct()], 2)
+    svt.check(st)
+    try:
+        st, t = svt.svt_ring_run(ring)
+        svt.check(st)
+        st, summ = svt.svt_result(ctx, t, -1)
+        rc, _, ws = oracle_lib.fit_batch(b, c)
+        assert st == svt.SVT_E_RANGE and rc == svt.SVT_E_RANGE
+        assert summ.err_road == ws["err_road"]
+    finally:
+        svt.svt_ring_destroy(ring)
