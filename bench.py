@@ -198,12 +198,12 @@ def section_fit(args, svt, synth, torch):
     rs = [r.struct() for r in results]
     stream = torch.cuda.current_stream().cuda_stream
     per_ring = max(1, min(args.ring_passes, args.steps))
-    warm = make_rings(svt, ctx, bs, rs, max(1, args.warmup), per_ring)
-    timed = make_rings(svt, ctx, bs, rs, args.steps, per_ring)
-    run_rings(svt, ctx, warm, stream)
+    warm = make_rings(svt, ctx.handle, bs, rs, max(1, args.warmup), per_ring)
+    timed = make_rings(svt, ctx.handle, bs, rs, args.steps, per_ring)
+    run_rings(svt, ctx.handle, warm, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    total, dev = run_rings(svt, ctx, timed, stream)
+    total, dev = run_rings(svt, ctx.handle, timed, stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for ring, _ in warm + timed:
@@ -313,10 +313,10 @@ def section_sweep(args, svt, synth, torch, iostudy):
         n_copy = 8
         dbs = [svt.to_device(batch) for _ in range(n_copy)]
         drs = [svt.DeviceResults(batch.n_events, batch.n_roads) for _ in range(n_copy)]
-        rings = make_rings(svt, ctx, [d.struct() for d in dbs], [r.struct() for r in drs],
+        rings = make_rings(svt, ctx.handle, [d.struct() for d in dbs], [r.struct() for r in drs],
                            100, 100)
-        run_rings(svt, ctx, rings, stream)
-        _, dev = run_rings(svt, ctx, rings, stream, repeat=3)
+        run_rings(svt, ctx.handle, rings, stream)
+        _, dev = run_rings(svt, ctx.handle, rings, stream, repeat=3)
         for ring, _ in rings:
             svt.svt_ring_destroy(ring)
         fit_us = float(np.median(dev)) / 1e3 / 100

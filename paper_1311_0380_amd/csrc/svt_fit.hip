@@ -31,18 +31,14 @@
 namespace svt {
 namespace {
 
-constexpr int kBins = 17 * 17;   // (n2, n3) in 0..16 x 0..16
+constexpr int kBins = 16 * 16;   // inner trip counts (n_a, n_b), each 1..16
 constexpr int kWaves = kBlock / 64;
+constexpr int kHitVecs = kHitCap / 8;            // 16-byte groups of the staged hit window
+constexpr int kVecsPerThread = kHitVecs / kBlock;
 static_assert(kMaxEventsPerChunk <= kBlock, "one thread per event of a chunk");
+static_assert(kHitVecs % kBlock == 0, "the hit window is a whole number of 16-byte groups per thread");
 
-// Inclusive scans across the wavefront: of two packed 32-bit counters
-// (neither half may overflow), and of one 64-bit value.
-__device__ __forceinline__ uint64_t wave_incl_scan_pair(uint64_t x)
-{
-    const uint32_t lo = wave_incl_scan((uint32_t)x), hi = wave_incl_scan((uint32_t)(x >> 32));
-    return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
+// Inclusive scan across the wavefront of one 64-bit value.
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x)
 {
     const int lane = threadIdx.x & 63;
@@ -54,12 +50,11 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x)
     return x;
 }
 
-// Block-wide exclusive scan: of packed 32-bit pairs (PAIR) or of 64-bit values.
-template <bool PAIR>
-__device__ uint64_t block_excl_scan(uint64_t v, uint64_t *s_warp, uint64_t &total)
+// Block-wide exclusive scan of 64-bit values (the comb_offsets kernels).
+__device__ uint64_t block_excl_scan64(uint64_t v, uint64_t *s_warp, uint64_t &total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint64_t incl = PAIR ? wave_incl_scan_pair(v) : wave_incl_scan64(v);
+    uint64_t incl = wave_incl_scan64(v);
     if (lane == 63) s_warp[wid] = incl;
     __syncthreads();
     uint64_t before = 0, tot = 0;
@@ -84,44 +79,166 @@ struct Acc {
 
 struct Shared {
     double base[3][kSubRoads];              // b + A[:,4] x4 + A[:,5] x5, rows 3..5
-    // per road: staged hit index of the first hit of layers a, b (x) and
-    // c, d (y); n_a | n_b << 8 | (a | b << 2 | c << 4 | d << 6) << 16 (z);
-    // sector (w)
-    uint4 rec[kSubRoads];
+    // per road, what its rows need (indices into the hit window and into
+    // the constants image, in doubles):
+    //   x  first hit of row layer c | of d << 16
+    //   y  first hit of inner layer a | of b << 16
+    //   z  column c of rows 3..5 | column d << 16
+    //   w  column a | column b << 16
+    uint4 ra[kSubRoads];
+    uint32_t shape[kSubRoads];              // n_a | n_b << 5 | key place of a << 10 | of b << 14
     unsigned long long key[kSubRoads];      // best key of each road
-    uint32_t n4[kSubRoads];                 // packed hit counts of each road
     uint32_t np[kSubRoads];                 // passing combinations of each road
-    uint16_t hb[kSubRoads];                 // first staged hit of each road
-    uint16_t row[kRowCap];                  // road | i0 << 8 | i1 << 12, binned by (n2, n3)
-    int16_t hit[kHitCap + 16];              // staged hit words (+ pad read by row loops)
-    uint32_t bin[kBins];
-    uint32_t bstart[kBins];
+    uint32_t n4[kSubRoads];                 // hit counts of each road (0 if malformed)
+    uint32_t info[kSubRoads];               // window position of its first hit | sector << 16
+    // rows, binned by (n_b, n_a): road | i_c << 8 | i_d << 12 | the row's key bits << 16
+    uint32_t row[kRowCap];
+    __align__(16) int16_t hit[kHitCap + 16];   // staged hit window (+ pad read by row loops)
+    __align__(16) uint32_t bin[kBins];
     int32_t evro[kMaxEventsPerChunk + 1];
     uint32_t evcnt[kMaxEventsPerChunk];
-    uint64_t warp[kWaves];
-    uint32_t fitc[kWaves];
-    int32_t misc[4];
+    uint32_t wrows[kWaves];                 // rows of each wavefront's roads
+    uint32_t wout[kWaves];                  // first lane of each wavefront outside the window
+    uint32_t wfit[kWaves];                  // first lane of each wavefront that does not fit
+    int32_t misc[4];                        // [2]: a staged word is out of range; [3]: rows
 };
 
-constexpr int kStage = kHitCap / kBlock;    // staged hits per thread
+// OR across the wavefront (all lanes active), as a uniform value.
+__device__ __forceinline__ uint32_t wave_or(uint32_t x)
+{
+    x |= dpp<kRowShr + 1, 0xF, true>(x);
+    x |= dpp<kRowShr + 2, 0xF, true>(x);
+    x |= dpp<kRowShr + 4, 0xF, true>(x);
+    x |= dpp<kRowShr + 8, 0xF, true>(x);
+    x |= dpp<kRowBcast15, 0xA, false>(x);
+    x |= dpp<kRowBcast31, 0xC, false>(x);
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+// Small rows of different trip counts in one wavefront (N2 and N3 at least
+// every lane's n2 and n3).  Indices past a lane's lists read the words that
+// follow them (the window carries a pad); those combinations get an
+// infinite index fraction, so they neither pass nor win, and the count
+// needs no mask.  The minimum keeps i3 / 256 per combination and adds
+// i2 / 16 once per i2.
+template <int N2, int N3>
+__device__ __forceinline__ void frac_small_masked(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                                  uint32_t n2, uint32_t n3, double lim)
+{
+    double h2[N2], h3[N3], f3[N3];
+#pragma unroll
+    for (int i = 0; i < N2; ++i) h2[i] = (double)hit[p2 + i];
+#pragma unroll
+    for (int i = 0; i < N3; ++i) {
+        h3[i] = (double)hit[p3 + i];
+        f3[i] = (uint32_t)i < n3 ? i * (1.0 / 256) : __builtin_inf();
+    }
+#pragma unroll
+    for (int i2 = 0; i2 < N2; ++i2) {
+        if (i2 == 0 || (uint32_t)i2 < n2) {
+            const double q3 = fma(st.a3, h2[i2], st.z3);
+            const double q4 = fma(st.a4, h2[i2], st.z4);
+            const double q5 = fma(st.a5, h2[i2], st.z5);
+            double bi = __builtin_inf();
+#pragma unroll
+            for (int i3 = 0; i3 < N3; ++i3) {
+                const double y3 = fma(st.c3, h3[i3], q3);
+                const double y4 = fma(st.c4, h3[i3], q4);
+                const double y5 = fma(st.c5, h3[i3], q5);
+                const double v = fma(y5, y5, fma(y4, y4, fma(y3, y3, f3[i3])));
+                count_le(st.np, v, lim);
+                bi = dmin(bi, v);
+            }
+            st.best = dmin(st.best, i2 == 0 ? bi : bi + i2 * (1.0 / 16));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// The row loops of one wavefront: its rows are sorted by (n3, n2), so when
+// every lane has the same n3 the last lane holds the largest n2; otherwise
+// the largest of each comes from one OR of one-hot bits.
+template <bool F>
+__device__ __forceinline__ void run_rows(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
+                                         uint32_t rn2, uint32_t rn3, double lim)
+{
+    const uint32_t n3f = __builtin_amdgcn_readfirstlane(rn3);
+    const uint32_t n3l = __builtin_amdgcn_readlane(rn3, 63);
+    const bool uni = n3f == n3l;
+    uint32_t n2m = __builtin_amdgcn_readlane(rn2, 63), n3m = n3l;
+    if (!uni) {
+        const uint32_t m = wave_or((1u << (rn2 - 1u)) | (1u << (rn3 + 15u)));
+        n2m = 32u - (uint32_t)__builtin_clz((m & 0xFFFFu) | 1u);
+        n3m = 32u - (uint32_t)__builtin_clz((m >> 16) | 1u);
+    }
+    if constexpr (F) {
+        if (n2m <= 4 && n3m <= 4) {
+            const uint32_t sel = ((n2m - 1) << 2) | (n3m - 1);
+#define SVT_SMALL(N2, N3)                                                         \
+    case ((N2 - 1) << 2) | (N3 - 1):                                              \
+        if (uni) frac_small<N2, N3, true>(st, hit, p2, p3, rn2, rn3, lim);        \
+        else frac_small_masked<N2, N3>(st, hit, p2, p3, rn2, rn3, lim);           \
+        return;
+            switch (sel) {
+                SVT_SMALL(1, 1) SVT_SMALL(1, 2) SVT_SMALL(1, 3) SVT_SMALL(1, 4)
+                SVT_SMALL(2, 1) SVT_SMALL(2, 2) SVT_SMALL(2, 3) SVT_SMALL(2, 4)
+                SVT_SMALL(3, 1) SVT_SMALL(3, 2) SVT_SMALL(3, 3) SVT_SMALL(3, 4)
+                SVT_SMALL(4, 1) SVT_SMALL(4, 2) SVT_SMALL(4, 3) SVT_SMALL(4, 4)
+            default: break;
+            }
+#undef SVT_SMALL
+        }
+    }
+    if (uni) {
+#define SVT_CASE(N)                                                          \
+    case N:                                                                  \
+        if constexpr (F) frac_uniform<N>(st, hit, p2, p3, rn2, n2m, lim);    \
+        else gen_uniform<N>(st, hit, p2, p3, rn2, n2m, lim);                 \
+        break;
+        switch (n3f) {
+            SVT_CASE(1) SVT_CASE(2) SVT_CASE(3) SVT_CASE(4) SVT_CASE(5) SVT_CASE(6)
+            SVT_CASE(7) SVT_CASE(8) SVT_CASE(9) SVT_CASE(10) SVT_CASE(11) SVT_CASE(12)
+            SVT_CASE(13) SVT_CASE(14) SVT_CASE(15) SVT_CASE(16)
+        default: break;
+        }
+#undef SVT_CASE
+    } else {
+        if constexpr (F) frac_mixed(st, hit, p2, p3, rn2, rn3, n2m, n3m, lim);
+        else gen_mixed(st, hit, p2, p3, rn2, rn3, n2m, n3m, lim);
+    }
+}
+
+// Hit words a in [0, 4096): no bit of 15..12 set in either half of a word pair.
+__device__ __forceinline__ bool words_ok(uint32_t pair) { return (pair & 0xF000F000u) == 0u; }
 
 // Process the roads [s, rb) of the current chunk starting at road s; returns
 // how many roads were fitted (at least one when s < rb).
+//
+// copy_image: the block's first sub-chunk also stages the sector constants
+// image into LDS, issued after its own loads so that the two latencies
+// overlap (the image is first read after the sub-chunk's first barrier).
 template <bool F>
-__device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int32_t s, int32_t rb,
+__device__ int process_sub(const FitArgs &a, Shared &S, double *s_cd, int32_t s, int32_t rb,
                            int32_t n_roads, int32_t n_hits, int32_t n_sectors, int32_t ne,
-                           double cut, Acc &acc)
+                           double cut, bool vec, bool copy_image, Acc &acc)
 {
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
     const int32_t r = s + tid;
     const bool inr = r < rb;
 
-    // one round of loads: the sub-chunk's hit range (uniform), each thread's
-    // road, and a speculative copy of the hits the next kSubRoads roads hold
+    // The hit window of the sub-chunk: from the first road's first hit,
+    // rounded down to a 16-byte boundary, to the end of the last road the
+    // sub-chunk can hold (at least the first road's end), at most kHitCap
+    // words.  A road inside the window finds its hits at their offset from
+    // the window's start.
     const int32_t s_end = min(rb, s + kSubRoads);
     const int32_t hs = clampi(a.hit_offsets[s], 0, n_hits);
-    const int32_t he = clampi(a.hit_offsets[s_end], hs, n_hits);
-    const int32_t t_pre = min(he - hs, kHitCap);
+    const int32_t hw = hs & ~7;
+    const int32_t he = clampi(max(a.hit_offsets[s_end], a.hit_offsets[s + 1]), hs, n_hits);
+    const int32_t W = min(he - hw, kHitCap);
+
+    // one round of loads: each thread's road and its share of the window
     uint32_t sec = 0, nh4 = 0, x2 = 0;
     int32_t h0 = 0, h1 = 0;
     if (inr) {
@@ -131,11 +248,33 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         h1 = a.hit_offsets[r + 1];
         x2 = a.xft2[r];
     }
-    int16_t v[kStage];
+    uint4 hv[kVecsPerThread];
 #pragma unroll
-    for (int q = 0; q < kStage; ++q) {
-        const int t = tid + q * kBlock;
-        v[q] = t < t_pre ? a.hits[hs + t] : (int16_t)0;
+    for (int q = 0; q < kVecsPerThread; ++q) {
+        int32_t t = 8 * (tid + q * kBlock);
+        // recomputed per sub-chunk: a per-lane address hoisted out of the
+        // chunk loop would stay live across the row loops
+        asm volatile("" : "+v"(t));
+        hv[q] = make_uint4(0u, 0u, 0u, 0u);
+        if (vec && t + 8 <= W) {
+            hv[q] = *reinterpret_cast<const uint4 *>(a.hits + hw + t);
+        } else if (t < W) {
+            // the window's last, partial group (or a hits array that is not
+            // 16-byte aligned): word by word, zeros past the window
+            uint64_t lo = 0, hi = 0;
+            for (int i = 0; i < 8 && t + i < W; ++i) {
+                const uint64_t v = (uint16_t)a.hits[hw + t + i];
+                if (i < 4) lo |= v << (16 * i);
+                else hi |= v << (16 * (i - 4));
+            }
+            hv[q] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+        }
+    }
+    if (copy_image) {
+        const uint4 *csrc = reinterpret_cast<const uint4 *>(a.cst_block);
+        uint4 *cdst = reinterpret_cast<uint4 *>(s_cd);
+        const int n16 = n_sectors * kCstBytesPerSector / 16;
+        for (int i = tid; i < n16; i += kBlock) cdst[i] = csrc[i];
     }
 
     const uint32_t n0 = nh4 & 255u, n1 = (nh4 >> 8) & 255u, n2 = (nh4 >> 16) & 255u,
@@ -148,218 +287,184 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
     ok = ok && xa >= 0 && xa < 4096 && xb >= 0 && xb < 4096;
     acc.err_road = min(acc.err_road, wave_min(inr && !ok ? (uint32_t)r : 0xFFFFFFFFu));
 
-    const uint32_t nh = ok ? sum : 0u;
     // row layers c < d: the two with the fewest hits (ties to the lower
-    // layer); inner layers a < b: the other two
-    uint32_t rowmask = 0;
-    {
-        const uint32_t nl[4] = {n0, n1, n2, n3};
+    // layer); inner layers a < b: the other two.  Keys n << 2 | layer are
+    // distinct, so a min / max network orders them.
+    const uint32_t k0 = n0 << 2, k1 = (n1 << 2) | 1u, k2 = (n2 << 2) | 2u, k3 = (n3 << 2) | 3u;
+    const uint32_t lo01 = min(k0, k1), hi01 = max(k0, k1), lo23 = min(k2, k3), hi23 = max(k2, k3);
+    const uint32_t q1 = min(lo01, lo23), q4 = max(hi01, hi23);
+    const uint32_t m1 = max(lo01, lo23), m2 = min(hi01, hi23);
+    const uint32_t q2 = min(m1, m2), q3 = max(m1, m2);
+    const bool rsw = (q1 & 3u) > (q2 & 3u), isw = (q3 & 3u) > (q4 & 3u);
+    const uint32_t kc = rsw ? q2 : q1, kd = rsw ? q1 : q2, ka = isw ? q4 : q3, kb = isw ? q3 : q4;
+    const uint32_t nh = ok ? sum : 0u;
+    const uint32_t rows = (ok && (q1 >> 2) != 0u) ? (kc >> 2) * (kd >> 2) : 0u;
+    const int32_t pos = h0 - hw;
+    const bool in_window = nh == 0u || (pos >= 0 && pos + (int32_t)nh <= W);
+
+    // rows before each road (the row list's capacity) and the first road
+    // outside the window, per wavefront
+    const uint32_t incl = wave_incl_scan(rows);
+    const uint64_t out = __ballot(inr && !in_window);
+    if (lane == 63) S.wrows[wid] = incl;
+    if (lane == 0) S.wout[wid] = out ? (uint32_t)__ffsll((unsigned long long)out) - 1u : 64u;
+    // stage the window (checking each word's range on the way)
+    bool bad_word = false;
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            uint32_t rk = 0;
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (m != l) rk += (nl[m] < nl[l] || (nl[m] == nl[l] && m < l)) ? 1u : 0u;
-            rowmask |= (rk < 2 ? 1u : 0u) << l;
+    for (int q = 0; q < kVecsPerThread; ++q) {
+        const int32_t t = 8 * (tid + q * kBlock);
+        if (t < W) {
+            *reinterpret_cast<uint4 *>(&S.hit[t]) = hv[q];
+            bad_word |= !words_ok(hv[q].x | hv[q].y | hv[q].z | hv[q].w);
         }
     }
-    // the layers and their counts are derived again where they are used,
-    // which keeps only the mask live across the scan's barriers
-    auto lay = [](uint32_t m, int q) {   // q = 0..3: c, d, a, b
-        return q == 0 ? (uint32_t)__builtin_ctz(m)
-             : q == 1 ? 31u - (uint32_t)__builtin_clz(m)
-             : q == 2 ? (uint32_t)__builtin_ctz(m ^ 15u) : 31u - (uint32_t)__builtin_clz(m ^ 15u);
-    };
-    auto cnt = [](uint32_t c4, uint32_t l) { return (c4 >> (8 * l)) & 255u; };
-    auto off = [](uint32_t c4, uint32_t l) {   // hits of the layers before l
-        return ((c4 & ((1u << (8 * l)) - 1u)) * 0x01010101u) >> 24;
-    };
-    const uint32_t rows =
-        (ok && n0 * n1 * n2 * n3 > 0) ? cnt(nh4, lay(rowmask, 0)) * cnt(nh4, lay(rowmask, 1)) : 0u;
-    // block scan of (hits, rows); the roads that fit are a prefix of the
-    // block, counted per wave and summed across the scan's second barrier
-    const uint64_t pk = (uint64_t)nh | ((uint64_t)rows << 32);
-    const uint64_t incl = wave_incl_scan_pair(pk);
-    const int lane = tid & 63, wid = tid >> 6;
-    if (lane == 63) S.warp[wid] = incl;
+    if (bad_word) S.misc[2] = 1;
     __syncthreads();
-    uint64_t before = 0;
+    uint32_t before = 0, total = 0, first_out = kBlock;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) before += (w < wid) ? S.warp[w] : 0ull;
-    const uint64_t ex = before + incl - pk;
-    const uint32_t hb = (uint32_t)ex, rbase = (uint32_t)(ex >> 32);
-    const bool fits = inr && hb + nh <= (uint32_t)kHitCap && rbase + rows <= (uint32_t)kRowCap;
-    const uint32_t wfit = (uint32_t)__popcll(__ballot(fits));
-    if (lane == 0) S.fitc[wid] = wfit;
-    __syncthreads();
-    int L = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) L += (int)S.fitc[w];
-    const bool active = tid < L;   // fits is a prefix of the block
-
-    if (tid == L - 1) {
-        S.misc[1] = (int32_t)(hb + nh);           // hits of the sub-chunk
-        S.misc[3] = (int32_t)(rbase + rows);      // rows of the sub-chunk
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t t = S.wrows[w], o = S.wout[w];
+        before += w < wid ? t : 0u;
+        total += t;
+        first_out = (first_out == (uint32_t)kBlock && o < 64u) ? (uint32_t)(w * 64) + o : first_out;
     }
-    const uint32_t bkey = cnt(nh4, lay(rowmask, 3)) * 17u + cnt(nh4, lay(rowmask, 2));   // n_b major
+    const uint32_t rbase = before + incl - rows;
+    // the roads that fit (their hits inside the window, their rows inside
+    // the row list) are a prefix [0, L) of the sub-chunk
+    int L = min(kBlock, rb - s);
+    if (total > (uint32_t)kRowCap || first_out < (uint32_t)kBlock) {
+        const bool fit = inr && in_window && rbase + rows <= (uint32_t)kRowCap;
+        const uint64_t m = __ballot(!fit);
+        if (lane == 0) S.wfit[wid] = m ? (uint32_t)__ffsll((unsigned long long)m) - 1u : 64u;
+        __syncthreads();
+        L = kBlock;
+#pragma unroll
+        for (int w = kWaves - 1; w >= 0; --w) {
+            const uint32_t f = S.wfit[w];
+            L = f < 64u ? w * 64 + (int)f : L;
+        }
+    }
+    const bool active = tid < L;
+    if (tid == L - 1) S.misc[3] = (int32_t)(rbase + rows);    // rows of the sub-chunk
+
+    const uint32_t lc = kc & 3u, ld = kd & 3u, la = ka & 3u, lb = kb & 3u;
+    const uint32_t bkey = ((kb >> 2) - 1u) * 16u + ((ka >> 2) - 1u);
     uint32_t boff = 0;
     if (active) {
-        S.hb[tid] = (uint16_t)hb;
-        {
-            const uint32_t lc = lay(rowmask, 0), ld = lay(rowmask, 1), la = lay(rowmask, 2),
-                           lb = lay(rowmask, 3);
-            S.rec[tid] = make_uint4((hb + off(nh4, la)) | ((hb + off(nh4, lb)) << 16),
-                                    (hb + off(nh4, lc)) | ((hb + off(nh4, ld)) << 16),
-                                    cnt(nh4, la) | (cnt(nh4, lb) << 8) |
-                                        ((la | (lb << 2) | (lc << 4) | (ld << 6)) << 16),
-                                    ok ? sec : 0u);
-        }
-        S.n4[tid] = ok ? nh4 : 0u;
+        // window positions of each layer's first hit (layer-major lists)
+        auto lpos = [&](uint32_t l) {
+            return (uint32_t)pos + (((nh4 & ((1u << (8u * l)) - 1u)) * 0x01010101u) >> 24);
+        };
+        const uint32_t cb = (ok ? sec : 0u) * (uint32_t)kCstStride;
+        S.ra[tid] = make_uint4(lpos(lc) | (lpos(ld) << 16), lpos(la) | (lpos(lb) << 16),
+                               (cb + 3u * lc) | ((cb + 3u * ld) << 16),
+                               (cb + 3u * la) | ((cb + 3u * lb) << 16));
+        S.shape[tid] = (ka >> 2) | ((kb >> 2) << 5) | ((12u - 4u * la) << 10) | ((12u - 4u * lb) << 14);
         S.key[tid] = ~0ull;
         S.np[tid] = 0;
+        S.n4[tid] = ok ? nh4 : 0u;
+        S.info[tid] = (uint32_t)pos | (sec << 16);
         if (rows) boff = atomicAdd(&S.bin[bkey], rows);
         if (ok) {
             // constant part of the constraint rows, exact in int32
             const double *cs = s_cd + sec * kCstStride;
-            const int32_t *cb = reinterpret_cast<const int32_t *>(cs) + kCstIntB;
+            const int32_t *cbi = reinterpret_cast<const int32_t *>(cs) + kCstIntB;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                S.base[k][tid] = fma(cs[15 + k], (double)xb, fma(cs[12 + k], (double)xa, (double)cb[k]));
+                S.base[k][tid] = fma(cs[15 + k], (double)xb, fma(cs[12 + k], (double)xa, (double)cbi[k]));
         }
-    }
-#pragma unroll
-    for (int q = 0; q < kStage; ++q) {
-        const int t = tid + q * kBlock;
-        if (t < t_pre) S.hit[t] = v[q];
     }
     __syncthreads();
-    const int32_t T = S.misc[1], total_rows = S.misc[3];
-    // range of the hit words: the speculative copy, then hits it did not
-    // cover (only possible with inconsistent offsets), each checked by the
-    // thread that holds it
-    int32_t bad_t = INT32_MAX;
-#pragma unroll
-    for (int q = 0; q < kStage; ++q) {
-        const int t = tid + q * kBlock;
-        if (t < T && t < t_pre && (v[q] < 0 || v[q] >= 4096)) bad_t = min(bad_t, t);
+    const int32_t total_rows = S.misc[3];
+    if (S.misc[2]) {
+        // a word out of range in the window: each road checks its own words
+        bool bad = false;
+        if (active && nh)
+            for (uint32_t i = 0; i < nh; ++i) {
+                const int16_t w = S.hit[pos + (int32_t)i];
+                bad |= w < 0 || w >= 4096;
+            }
+        acc.err_road = min(acc.err_road, wave_min(bad ? (uint32_t)r : 0xFFFFFFFFu));
     }
-    for (int t = t_pre + tid; t < T; t += kBlock) {
-        const int32_t g = hs + t;
-        const int16_t h = g < n_hits ? a.hits[g] : (int16_t)0;
-        S.hit[t] = h;
-        if (h < 0 || h >= 4096) bad_t = min(bad_t, t);
-    }
-    uint32_t bad_hit_road = 0xFFFFFFFFu;
-    if (bad_t != INT32_MAX) {
-        int lo = 0, hi = L;     // last road with hb <= bad_t
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if ((int32_t)S.hb[mid] <= bad_t) lo = mid; else hi = mid;
-        }
-        bad_hit_road = (uint32_t)(s + lo);
-    }
-    acc.err_road = min(acc.err_road, wave_min(bad_hit_road));
-    // bin starts: every wavefront scans the 289 bins itself (lane l holds
-    // bins 5l .. 5l+4) and fetches its roads' starts across lanes, so no
-    // barrier separates the scan from the row lists
+    // bin starts: every wavefront scans the 256 bins itself (lane l holds
+    // bins 4l .. 4l+3); all write the same starts, so a wavefront reading
+    // after its own writes sees the right value whoever wrote last
     uint32_t bstart;
     {
-        uint32_t vb[5], loc = 0;
-        const int lb = (tid & 63) * 5;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            vb[q] = lb + q < kBins ? S.bin[lb + q] : 0u;
-            loc += vb[q];
-        }
-        uint32_t run = wave_incl_scan(loc) - loc;
-        // every wavefront writes the same starts, so a wavefront reading
-        // after its own writes sees the right value whoever wrote last
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            if (lb + q < kBins) S.bstart[lb + q] = run;
-            run += vb[q];
-        }
-        wave_sync();
-        bstart = S.bstart[bkey];
+        const uint4 vb = *reinterpret_cast<const uint4 *>(&S.bin[4 * lane]);
+        const uint32_t loc = vb.x + vb.y + vb.z + vb.w;
+        const uint32_t run = wave_incl_scan(loc) - loc;
+        // the start of bin 4 l + i is lane l's run plus its first i counts
+        const int o = (int)(bkey >> 2);
+        const uint32_t i = bkey & 3u;
+        const uint32_t r0 = (uint32_t)__shfl((int)run, o, 64), b0 = (uint32_t)__shfl((int)vb.x, o, 64),
+                       b1 = (uint32_t)__shfl((int)vb.y, o, 64), b2 = (uint32_t)__shfl((int)vb.z, o, 64);
+        bstart = r0 + (i > 0 ? b0 : 0u) + (i > 1 ? b1 : 0u) + (i > 2 ? b2 : 0u);
     }
-
-    // rows of the road, in (i_c, i_d) order, at its place in the binned list
+    // the road's rows, in (i_c, i_d) order, at its place in the binned list;
+    // each carries its key bits (i_c and i_d at their layers' places)
     if (active && rows) {
-        // the road's rows at [w, w + rows): an odd first slot alone, then
-        // two rows per 32-bit store
-        uint32_t w = bstart + boff, ic = 0, id = 0, k = 0;
-        const uint32_t base = (uint32_t)tid, nd = cnt(nh4, lay(rowmask, 1));
-        if (w & 1u) {
-            S.row[w++] = (uint16_t)base;
-            k = 1;
-            id = 1 == nd ? 0u : 1u;
-            ic = 1 == nd ? 1u : 0u;
+        const uint32_t nd = kd >> 2, sc = 12u - 4u * lc, sd = 12u - 4u * ld;
+        uint32_t w = bstart + boff, ic = 0, id = 0;
+        for (uint32_t k = 0; k < rows; ++k, ++w) {
+            S.row[w] = (uint32_t)tid | (ic << 8) | (id << 12) | (((ic << sc) | (id << sd)) << 16);
+            if (++id == nd) {
+                id = 0;
+                ++ic;
+            }
         }
-        for (; k + 1 < rows; k += 2, w += 2) {
-            const uint32_t ra = base | (ic << 8) | (id << 12);
-            if (++id == nd) { id = 0; ++ic; }
-            const uint32_t rb2 = base | (ic << 8) | (id << 12);
-            if (++id == nd) { id = 0; ++ic; }
-            *reinterpret_cast<uint32_t *>(&S.row[w]) = ra | (rb2 << 16);
-        }
-        if (k < rows) S.row[w] = (uint16_t)(base | (ic << 8) | (id << 12));
     }
     __syncthreads();
-    for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;   // ready for the next sub-chunk
+    S.bin[tid] = 0;   // ready for the next sub-chunk (kBins == kBlock)
+    if (tid == 0) S.misc[2] = 0;
 
     // B: every combination of every row
+    const double lim = F ? cut + 0.5 : cut;
     for (int idx0 = 0; idx0 < total_rows; idx0 += kBlock) {
         if (idx0 + (tid & ~63) >= total_rows) continue;   // whole wavefront idle
         const int idx = idx0 + tid;
         const bool act = idx < total_rows;
         const uint32_t d = S.row[act ? idx : total_rows - 1];
         const uint32_t j = d & 255u, ic = (d >> 8) & 15u, id = (d >> 12) & 15u;
-        const uint4 rc = S.rec[j];
-        const uint32_t rn2 = rc.z & 255u, rn3 = (rc.z >> 8) & 255u;
-        const uint32_t la = (rc.z >> 16) & 3u, lb = (rc.z >> 18) & 3u, lc = (rc.z >> 20) & 3u,
-                       ld = (rc.z >> 22) & 3u;
-        // sector constants: column l of rows 3..5 at cs[3 l .. 3 l + 2]
-        const double *cs = s_cd + rc.w * kCstStride;
-        const double *ka = cs + 3 * la, *kb = cs + 3 * lb, *kc = cs + 3 * lc, *kd = cs + 3 * ld;
-        const double hc = (double)S.hit[(rc.y & 0xFFFFu) + ic], hd = (double)S.hit[(rc.y >> 16) + id];
+        const uint4 ra = S.ra[j];
+        const uint32_t shp = S.shape[j];
+        const double *cc = s_cd + (ra.z & 0xFFFFu), *cd = s_cd + (ra.z >> 16);
+        const double *ca = s_cd + (ra.w & 0xFFFFu), *cb = s_cd + (ra.w >> 16);
+        const double hc = (double)S.hit[(ra.x & 0xFFFFu) + ic], hd = (double)S.hit[(ra.x >> 16) + id];
         Row st;
-        st.z3 = fma(kd[0], hd, fma(kc[0], hc, S.base[0][j]));
-        st.z4 = fma(kd[1], hd, fma(kc[1], hc, S.base[1][j]));
-        st.z5 = fma(kd[2], hd, fma(kc[2], hc, S.base[2][j]));
-        st.a3 = ka[0];
-        st.a4 = ka[1];
-        st.a5 = ka[2];
-        st.c3 = kb[0];
-        st.c4 = kb[1];
-        st.c5 = kb[2];
+        st.z3 = fma(cd[0], hd, fma(cc[0], hc, S.base[0][j]));
+        st.z4 = fma(cd[1], hd, fma(cc[1], hc, S.base[1][j]));
+        st.z5 = fma(cd[2], hd, fma(cc[2], hc, S.base[2][j]));
+        st.a3 = ca[0];
+        st.a4 = ca[1];
+        st.a5 = ca[2];
+        st.c3 = cb[0];
+        st.c4 = cb[1];
+        st.c5 = cb[2];
         st.best = F ? __builtin_inf() : cut + 1.0;
         st.bidx = 0xFFFFFFFFu;
         st.np = 0;
-        run_row<F>(st, S.hit, rc.x & 0xFFFFu, rc.x >> 16, rn2, rn3, F ? cut + 0.5 : cut);
+        run_rows<F>(st, S.hit, ra.y & 0xFFFFu, ra.y >> 16, shp & 31u, (shp >> 5) & 31u, lim);
         if (act) {
-            // the row's indices and layers come back from LDS rather than
-            // staying live across the row loops
-            const uint32_t d2 = S.row[idx];
-            const uint32_t j2 = d2 & 255u, lay = S.rec[j2].z >> 16;
-            const uint32_t rowbits = (((d2 >> 8) & 15u) << (12u - 4u * ((lay >> 4) & 3u))) |
-                                     (((d2 >> 12) & 15u) << (12u - 4u * ((lay >> 6) & 3u)));
+            // the key places come back from LDS rather than staying live
+            // across the row loops
+            const uint32_t shp2 = S.shape[j];
             unsigned long long key;
-            if (row_key<F>(st, cut, rowbits, 12u - 4u * (lay & 3u), 12u - 4u * ((lay >> 2) & 3u), key))
-                atomicMin(&S.key[j2], key);
-            if (st.np) atomicAdd(&S.np[j2], st.np);
+            if (row_key<F>(st, cut, d >> 16, (shp2 >> 10) & 15u, (shp2 >> 14) & 15u, key))
+                atomicMin(&S.key[j], key);
+            if (st.np) atomicAdd(&S.np[j], st.np);
         }
     }
     __syncthreads();
 
-    // C: results of each road.  Its counts, hit base and sector come back
-    // from LDS (zero counts for a malformed road give the same outputs as
-    // the road's error path), which keeps phase A's values out of phase B.
+    // C: results of each road.  Its counts, first hit and sector come back
+    // from LDS (zero counts for a malformed road give the same outputs
+    // as the road's error path), which keeps phase A's values out of phase B.
     uint32_t my_comb = 0, my_pass = 0, my_track = 0;
     if (active) {
-        const uint32_t c4 = S.n4[tid], hb = S.hb[tid], sec = S.rec[tid].w;
-        const uint32_t n0 = c4 & 255u, n1 = (c4 >> 8) & 255u, n2 = (c4 >> 16) & 255u,
-                       n3 = c4 >> 24;
-        const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
+        const uint32_t c4 = S.n4[tid];
+        const uint32_t c0 = c4 & 255u, c1 = (c4 >> 8) & 255u, c2n = (c4 >> 16) & 255u,
+                       c3 = c4 >> 24;
         const unsigned long long key = S.key[tid];
         const uint32_t np = S.np[tid];
         const bool found = key != ~0ull;
@@ -371,15 +476,17 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
             const uint32_t i0 = (uint32_t)(key >> 12) & 15u, i1 = (uint32_t)(key >> 8) & 15u,
                            i2 = (uint32_t)(key >> 4) & 15u, i3 = (uint32_t)key & 15u;
             c2 = key >> 16;
-            bk = (int32_t)(((i0 * n1 + i1) * n2 + i2) * n3 + i3);
+            bk = (int32_t)(((i0 * c1 + i1) * c2n + i2) * c3 + i3);
             hi4 = i0 | (i1 << 8) | (i2 << 16) | (i3 << 24);
-            const uint32_t x[6] = {(uint32_t)(int32_t)S.hit[hb + i0],
-                                   (uint32_t)(int32_t)S.hit[hb + n0 + i1],
-                                   (uint32_t)(int32_t)S.hit[hb + n0 + n1 + i2],
-                                   (uint32_t)(int32_t)S.hit[hb + n0 + n1 + n2 + i3],
+            const uint32_t inf = S.info[tid];
+            const int32_t hp = (int32_t)(inf & 0xFFFFu);
+            const uint32_t x[6] = {(uint32_t)(int32_t)S.hit[hp + i0],
+                                   (uint32_t)(int32_t)S.hit[hp + c0 + i1],
+                                   (uint32_t)(int32_t)S.hit[hp + c0 + c1 + i2],
+                                   (uint32_t)(int32_t)S.hit[hp + c0 + c1 + c2n + i3],
                                    (uint32_t)xa, (uint32_t)xb};
             // parameter rows 0..2, exact in int32 by the load-time bound
-            const int32_t *ci = reinterpret_cast<const int32_t *>(s_cd + sec * kCstStride);
+            const int32_t *ci = reinterpret_cast<const int32_t *>(s_cd + (inf >> 16) * kCstStride);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 uint32_t acc32 = (uint32_t)ci[kCstIntPB + k];
@@ -391,7 +498,7 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
         }
         // results are written once and not read again by this kernel:
         // streaming stores keep them from filling (and later flushing) L2
-        __builtin_nontemporal_store((int32_t)(n0 * n1 * n2 * n3), &a.ncomb[r]);
+        __builtin_nontemporal_store((int32_t)(c0 * c1 * c2n * c3), &a.ncomb[r]);
         __builtin_nontemporal_store((int32_t)np, &a.npass[r]);
         __builtin_nontemporal_store(bk, &a.best[r]);
         __builtin_nontemporal_store(c2, &a.chi2[r]);
@@ -407,7 +514,7 @@ __device__ int process_sub(const FitArgs &a, Shared &S, const double *s_cd, int3
             }
             atomicAdd(&S.evcnt[lo], 1u);
         }
-        my_comb = n0 * n1 * n2 * n3;
+        my_comb = c0 * c1 * c2n * c3;
         my_pass = np;
         my_track = found ? 1u : 0u;
     }
@@ -466,18 +573,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
 fit_kernel(FitArgs a)
 {
     extern __shared__ __align__(16) unsigned char s_dyn[];
-    __shared__ Shared S;
+    __shared__ __align__(16) Shared S;
     const int tid = threadIdx.x;
 
     int32_t n_events = a.n_events, n_roads = a.n_roads, n_hits = a.n_hits;
-    uint32_t seq = a.seq;
     if (a.sizes != nullptr) {
         n_events = a.sizes->n_events;
         n_roads = a.sizes->n_roads;
         n_hits = a.sizes->n_hits;
-        seq = a.sizes->seq;
     }
-    if (a.seq_dev != nullptr) seq = *a.seq_dev;
     const int32_t n_sectors = a.n_sectors;
     double *s_cd = reinterpret_cast<double *>(s_dyn);
 
@@ -541,9 +645,14 @@ fit_kernel(FitArgs a)
         if (tid + kBlock <= ne) ev1 = a.road_offsets[e0 + tid + kBlock];
     }
 
-    if (a.schedule != 3)
-        for (int i = tid; i < n16; i += kBlock) cdst[i] = csrc[i];
-    for (int i = tid; i < kBins; i += kBlock) S.bin[i] = 0;
+    // (with the cyclic and blocked schedules the first sub-chunk stages the
+    // sector constants, see process_sub)
+    bool copy_image = a.schedule != 3;
+    static_assert(kBins == kBlock, "one bin per thread");
+    S.bin[tid] = 0;
+    if (tid == 0) S.misc[2] = 0;
+    // 16-byte hit loads need a 16-byte aligned hits array
+    const bool vec = (reinterpret_cast<uintptr_t>(a.hits) & 15u) == 0u;
 
     if (c_first < c_last) {
         const int32_t ne = min(E, e_end - (e_base + c_first * E));
@@ -559,9 +668,10 @@ fit_kernel(FitArgs a)
         __syncthreads();
         const int32_t ra = clampi(S.evro[0], 0, n_roads);
         const int32_t rb = clampi(S.evro[ne], ra, n_roads);
-        for (int32_t s = ra; s < rb;)
-            s += a.frac_key ? process_sub<true>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc)
-                            : process_sub<false>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, acc);
+        for (int32_t s = ra; s < rb; copy_image = false)
+            s += a.frac_key
+                     ? process_sub<true>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, copy_image, acc)
+                     : process_sub<false>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, copy_image, acc);
         uint32_t bad_event = 0xFFFFFFFFu;
         for (int i = tid; i < ne; i += kBlock) {
             const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
@@ -592,7 +702,7 @@ fit_kernel(FitArgs a)
             p.err_road = min(p.err_road, s_part[w].err_road);
             p.err_event = min(p.err_event, s_part[w].err_event);
         }
-        p.seq = seq;
+        p.seq = request_seq(a);
         a.partials[blockIdx.x] = p;
     }
 }
@@ -630,7 +740,7 @@ __global__ void __launch_bounds__(kBlock) scan_tile_sums(int64_t *tile_sum, int3
         const int32_t b = b0 + threadIdx.x;
         const int64_t v = b < n_tiles ? tile_sum[b] : 0;
         uint64_t tot;
-        const int64_t ex = (int64_t)block_excl_scan<false>((uint64_t)v, warp, tot);
+        const int64_t ex = (int64_t)block_excl_scan64((uint64_t)v, warp, tot);
         if (b < n_tiles) tile_sum[b] = carry + ex;
         carry += (int64_t)tot;
     }
@@ -647,7 +757,7 @@ __global__ void __launch_bounds__(kBlock) scan_apply(const int32_t *ncomb, int32
         const int64_t g = base + i0 + threadIdx.x;
         const int64_t v = g < n ? ncomb[g] : 0;
         uint64_t tot;
-        const int64_t ex = (int64_t)block_excl_scan<false>((uint64_t)v, warp, tot);
+        const int64_t ex = (int64_t)block_excl_scan64((uint64_t)v, warp, tot);
         if (g < n) out[g] = carry + ex;
         carry += (int64_t)tot;
     }

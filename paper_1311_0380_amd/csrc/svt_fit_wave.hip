@@ -348,14 +348,11 @@ fit_wave_kernel(FitArgs a)
     const int tid = threadIdx.x;
 
     int32_t n_events = a.n_events, n_roads = a.n_roads, n_hits = a.n_hits;
-    uint32_t seq = a.seq;
     if (a.sizes != nullptr) {
         n_events = a.sizes->n_events;
         n_roads = a.sizes->n_roads;
         n_hits = a.sizes->n_hits;
-        seq = a.sizes->seq;
     }
-    if (a.seq_dev != nullptr) seq = *a.seq_dev;
     // the first chunk's event boundaries are in flight while the columns 0..3
     // of every sector's constraint rows are staged in LDS
     const int32_t n_chunks =
@@ -397,7 +394,7 @@ fit_wave_kernel(FitArgs a)
             p.err_road = min(p.err_road, s_part[w].err_road);
             p.err_event = min(p.err_event, s_part[w].err_event);
         }
-        p.seq = seq;
+        p.seq = request_seq(a);
         a.partials[blockIdx.x] = p;
     }
 }

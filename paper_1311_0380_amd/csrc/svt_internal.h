@@ -9,7 +9,7 @@ namespace svt {
 constexpr int kBlock = 256;        // threads per block (4 wave64)
 constexpr int kSubRoads = 256;     // roads per sub-chunk: one thread per road
 constexpr int kHitCap = 4096;      // hits staged in LDS per sub-chunk
-constexpr int kRowCap = 2048;      // (i0, i1) rows per sub-chunk
+constexpr int kRowCap = 1536;      // rows per sub-chunk (the block kernel's row list)
 constexpr int kMaxEventsPerChunk = 256;
 constexpr int kMaxBlocksPerCu = 16;
 constexpr int kTargetRoadsPerChunk = 256;
@@ -95,6 +95,19 @@ struct FitArgs {
     BlockPartial *partials;     // host-mapped, [gridDim.x]
     uint32_t seq;
 };
+
+// The sequence number a fit kernel writes into its partial sums: from the
+// ring's device word, the plan's host-mapped sizes or the launch arguments.
+// (Relaxed atomic loads: plain ones were merged into one load through a
+// pointer that could also point at a stack copy of a.seq.)
+__device__ __forceinline__ uint32_t request_seq(const FitArgs &a)
+{
+    if (a.seq_dev != nullptr)
+        return __hip_atomic_load(a.seq_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a.sizes != nullptr)
+        return __hip_atomic_load(&a.sizes->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return a.seq;
+}
 
 hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
 // start/stop non-NULL: the dispatch itself records them around the kernel

@@ -249,6 +249,25 @@ int auto_events_per_chunk(int32_t n_events, int32_t n_roads, int target, int max
     return e;
 }
 
+// Roads per chunk of the block kernel, from the work a road is expected to
+// hold.  With m hits per road on average, a road of four equal layers has
+// about (m / 4)^4 combinations (never fewer than that for unequal means).
+// A chunk aims at the batch's combinations spread over the grid's slots,
+// kept between 2048 and 10000 combinations, and at 16 to 256 roads:
+// 256-road chunks of 256-combination roads would leave most of the grid idle.
+int block_roads_per_chunk(int32_t n_roads, int32_t n_hits, int64_t slots)
+{
+    if (n_roads <= 0) return svt::kTargetRoadsPerChunk;
+    const double m = (double)n_hits / (double)n_roads / 4.0;
+    const double per_road = m * m * m * m > 1.0 ? m * m * m * m : 1.0;
+    double target = per_road * (double)n_roads / (double)(slots > 0 ? slots : 1);
+    target = target < 2048.0 ? 2048.0 : (target > 10000.0 ? 10000.0 : target);
+    int roads = (int)(target / per_road + 0.5);
+    if (roads < 16) roads = 16;
+    if (roads > svt::kTargetRoadsPerChunk) roads = svt::kTargetRoadsPerChunk;
+    return roads;
+}
+
 // Kernel, chunking and grid of a launch.  The wave kernel takes a chunk per
 // wavefront (4 per block), the block kernel a chunk per block.  A persistent
 // grid (graph plans) keeps the full size; otherwise the grid shrinks to the
@@ -259,7 +278,7 @@ struct LaunchShape {
     int grid;
 };
 
-LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int32_t nr,
+LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int32_t nr, int32_t nh,
                          bool persistent)
 {
     LaunchShape ls;
@@ -274,11 +293,12 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
         bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : svt::kWaveBlocksPerCu;
         per_block = svt::kBlock / 64;
     } else {
+        bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 3;
         ls.epc = t.events_per_chunk > 0
                      ? t.events_per_chunk
-                     : auto_events_per_chunk(ne, nr, svt::kTargetRoadsPerChunk,
+                     : auto_events_per_chunk(ne, nr,
+                                             block_roads_per_chunk(nr, nh, (int64_t)c->cu_count * bpc),
                                              svt::kMaxEventsPerChunk);
-        bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 3;
         per_block = 1;
     }
     int64_t grid = (int64_t)c->cu_count * bpc;
@@ -683,7 +703,7 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
         co_dev = static_cast<int64_t *>(const_cast<void *>(device_view(res->comb_offsets, k)));
     }
 
-    const LaunchShape ls = launch_shape(c, c->tuning, ne, nr, false);
+    const LaunchShape ls = launch_shape(c, c->tuning, ne, nr, nh, false);
     const int64_t grid = ls.grid;
     a.schedule = c->tuning.schedule;
     a.partials = static_cast<svt::BlockPartial *>(
@@ -1090,7 +1110,7 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
         if (tuning->schedule) p->tuning.schedule = tuning->schedule;
         p->tuning.kernel = tuning->kernel;
     }
-    const LaunchShape ls = launch_shape(c, p->tuning, max_events, max_roads, true);
+    const LaunchShape ls = launch_shape(c, p->tuning, max_events, max_roads, max_hits, true);
     p->const_gen = c->const_gen;
 
     // buffer layout: inputs, then results, then the size descriptor
@@ -1327,7 +1347,8 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     std::vector<LaunchShape> shapes(n_batches);
     std::vector<int> part_off(n_passes + 1, 0);
     for (int i = 0; i < n_batches; ++i)
-        shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads, false);
+        shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads,
+                                 batches[i].n_hits, false);
     for (int p = 0; p < n_passes; ++p) part_off[p + 1] = part_off[p] + shapes[p % n_batches].grid;
     r->total_parts = part_off[n_passes];
     svt_status st = dev_alloc(c, reinterpret_cast<void **>(&r->seq_dev), 256);
