@@ -223,6 +223,23 @@ svt_status svt_list_passing(svt_ctx *ctx, const svt_event_batch *batch, const in
                             const svt_pass_list *list, void *hip_stream, svt_ticket *ticket);
 
 /*
+ * svt_list_passing for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same contracts, results and errors, but the running sums
+ * of the pass counts go to a fixed 512 KiB scratch array that the library
+ * holds on each device until the process ends, so the call allocates
+ * nothing.  At most 2^24 roads: a larger batch returns SVT_E_NOMEM, and
+ * svt_last_error() names the limit.  Every call on one device shares that
+ * array, whatever its context or stream: calls that overlap on one device
+ * race, and the caller must not let them overlap (wait for one with
+ * svt_result before submitting the next).  SVT_E_STATE when the device has
+ * no scratch (device ordinals above 63).
+ */
+svt_status svt_list_passing_noalloc(svt_ctx *ctx, const svt_event_batch *batch,
+                                    const int32_t *npass, const svt_pass_list *list,
+                                    void *hip_stream, svt_ticket *ticket);
+
+/*
  * Packed input word stream (this library's own format; the paper's unpack
  * stage, Sec. 2.1, reads the experiment's raw words, whose format is not
  * given).  32-bit words, the top two bits a tag:

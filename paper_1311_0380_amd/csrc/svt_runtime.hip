@@ -43,6 +43,33 @@ svt_status hip_fail(hipError_t e, const char *what)
 
 constexpr int kSlots = 64;
 
+// Scratch of svt_list_passing_noalloc: the running sums of the pass counts
+// (one int64 per tile of svt::kListTile roads, plus the total) for at most
+// kNoAllocRoads roads, 512 KiB.  Every device holds its own copy until the
+// process ends.  Host code never uses the array's name as an address: it
+// uses the device address svt_create takes for each device.
+constexpr int32_t kNoAllocRoads = 1 << 24;
+constexpr int64_t kNoAllocWords = ((int64_t)kNoAllocRoads + svt::kListTile - 1) / svt::kListTile + 1;
+static __device__ __align__(256) int64_t scratch[(kNoAllocWords + 31) / 32 * 32];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int64_t *g_scratch_dev[kMaxDevices] = {};   // device address of `scratch` on each device
+
+// Once per device, with that device current: the device address of its copy
+// of the scratch array.
+svt_status scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return SVT_OK;   // no allocation-free calls there
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device] != nullptr) return SVT_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[device] = static_cast<int64_t *>(p);
+    return SVT_OK;
+}
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t cap = 0;
@@ -405,6 +432,13 @@ svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes)
         delete c;
         return hip_fail(e, "fit kernel attributes");
     }
+    {
+        const svt_status ss = scratch_setup(device);
+        if (ss != SVT_OK) {
+            delete c;
+            return ss;
+        }
+    }
     e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
@@ -745,8 +779,16 @@ svt_status svt_fit_events(svt_ctx *c, const svt_event_batch *b, const svt_result
     return SVT_OK;
 }
 
-svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t *npass,
-                            const svt_pass_list *list, void *hip_stream, svt_ticket *ticket)
+}  // extern "C"
+
+namespace {
+
+// Both list entry points: with fixed == NULL the running sums go to the
+// slot's scratch (allocated or grown here); otherwise to `fixed`, which
+// holds at least list_scratch_bytes(n_roads) (no allocation at all).
+svt_status list_submit(svt_ctx *c, const svt_event_batch *b, const int32_t *npass,
+                       const svt_pass_list *list, void *hip_stream, svt_ticket *ticket,
+                       int64_t *fixed)
 {
     if (c == nullptr || b == nullptr || list == nullptr || ticket == nullptr) return SVT_E_INVAL;
     const int32_t nr = b->n_roads, nh = b->n_hits;
@@ -767,8 +809,12 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     if (s.busy) return SVT_E_AGAIN;
     DeviceGuard g(c->device);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
-    svt_status r = ensure(c, s.scan, svt::list_scratch_bytes(nr));
-    if (r != SVT_OK) return r;
+    int64_t *scan = fixed;
+    if (scan == nullptr) {
+        const svt_status r = ensure(c, s.scan, svt::list_scratch_bytes(nr));
+        if (r != SVT_OK) return r;
+        scan = static_cast<int64_t *>(s.scan.ptr);
+    }
 
     svt::ListArgs a;
     memset(&a, 0, sizeof a);
@@ -802,7 +848,7 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); }, [] {});
     guard.enqueuing();
     HIP_TRY(hipEventRecord(s.ev_start, st));
-    hipError_t e = svt::launch_list(a, (int)grid, static_cast<int64_t *>(s.scan.ptr), st);
+    hipError_t e = svt::launch_list(a, (int)grid, scan, st);
     if (e != hipSuccess) return hip_fail(e, "list kernel launch");
     HIP_TRY(hipEventRecord(s.ev_end, st));
     guard.submitted();
@@ -815,6 +861,33 @@ svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t 
     s.ticket = c->next_ticket++;
     *ticket = s.ticket;
     return SVT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+svt_status svt_list_passing(svt_ctx *c, const svt_event_batch *b, const int32_t *npass,
+                            const svt_pass_list *list, void *hip_stream, svt_ticket *ticket)
+{
+    return list_submit(c, b, npass, list, hip_stream, ticket, nullptr);
+}
+
+svt_status svt_list_passing_noalloc(svt_ctx *c, const svt_event_batch *b, const int32_t *npass,
+                                    const svt_pass_list *list, void *hip_stream, svt_ticket *ticket)
+{
+    if (c == nullptr || b == nullptr) return SVT_E_INVAL;
+    if (b->n_roads > kNoAllocRoads) {
+        g_last_error = "svt_list_passing_noalloc: more than 2^24 roads (its scratch holds the "
+                       "running sums of at most 2^24 roads)";
+        return SVT_E_NOMEM;
+    }
+    int64_t *p = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_dev[c->device] : nullptr;
+    if (p == nullptr) {
+        g_last_error = "svt_list_passing_noalloc: no scratch on this device";
+        return SVT_E_STATE;
+    }
+    return list_submit(c, b, npass, list, hip_stream, ticket, p);
 }
 
 svt_status svt_unpack_stream(svt_ctx *c, const uint32_t *words, int64_t n_words, int32_t mem_kind,

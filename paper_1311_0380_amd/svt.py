@@ -86,6 +86,9 @@ SIGNATURES = {
     "svt_list_passing": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch), P,
                                           ctypes.POINTER(svt_pass_list), P,
                                           ctypes.POINTER(ctypes.c_int64)]),
+    "svt_list_passing_noalloc": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch), P,
+                                                  ctypes.POINTER(svt_pass_list), P,
+                                                  ctypes.POINTER(ctypes.c_int64)]),
     "svt_unpack_stream": (ctypes.c_int32, [P, P, ctypes.c_int64, ctypes.c_int32,
                                            ctypes.POINTER(svt_unpack_out), P,
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -347,6 +350,14 @@ def svt_list_passing(ctx, batch: svt_event_batch, npass_ptr: int, lst: svt_pass_
     t = ctypes.c_int64(0)
     st = lib.svt_list_passing(ctx, ctypes.byref(batch), P(npass_ptr), ctypes.byref(lst),
                               None if stream is None else P(stream), ctypes.byref(t))
+    return st, t.value
+
+
+def svt_list_passing_noalloc(ctx, batch: svt_event_batch, npass_ptr: int, lst: svt_pass_list,
+                             stream=None):
+    t = ctypes.c_int64(0)
+    st = lib.svt_list_passing_noalloc(ctx, ctypes.byref(batch), P(npass_ptr), ctypes.byref(lst),
+                                      None if stream is None else P(stream), ctypes.byref(t))
     return st, t.value
 
 
