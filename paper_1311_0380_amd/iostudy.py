@@ -88,3 +88,33 @@ def round_trip(ctx: svt.Context, batch, event_counts=(1, 10, 100, 300, 1000, 300
                              fit_us=fit_us,
                              transfer_share=max(0.0, 1.0 - fit_us / rt_us) if rt_us > 0 else None))
     return rows
+
+
+def main():
+    """python -m paper_1311_0380_amd.iostudy [--kind pageable|pinned|mapped|all]
+    Transfer latencies (median of --reps, timed by events on the context's
+    stream) as one JSON line, for profiling the transfers on their own."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kind", default="all", choices=["pageable", "pinned", "mapped", "all"])
+    ap.add_argument("--reps", type=int, default=9)
+    args = ap.parse_args()
+    kinds = [k for k, name in KIND_NAMES.items() if args.kind in (name, "all") and
+             k != svt.SVT_MEM_DEVICE]
+    ctx = svt.Context(0)
+    try:
+        rows = []
+        for kind in kinds:
+            for direction in (0, 1):
+                for n in DEFAULT_SIZES:
+                    us = svt.svt_io_probe(ctx.handle, kind, direction, n, args.reps)
+                    rows.append(dict(kind=KIND_NAMES[kind], dir="h2d" if direction == 0 else "d2h",
+                                     bytes=int(n), us=us, gbs=n / us / 1e3))
+        print(json.dumps({"reps": args.reps, "transfers": rows}))
+    finally:
+        ctx.close()
+
+
+if __name__ == "__main__":
+    main()
