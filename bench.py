@@ -138,16 +138,18 @@ def cpu_baseline(batch, consts, min_seconds=10.0):
             "cpu_model": cpu["model"], "nproc": cpu["nproc"], "affinity": cpu["affinity"]}
 
 
-def make_rings(svt, ctx, bs, rs, steps, per_ring):
+def make_rings(svt, ctx, bs, rs, steps, per_ring, per_launch=0):
     """Rings covering `steps` passes: full rings of per_ring passes (each
-    starting at a different copy) and one ring for the remainder."""
+    starting at a different copy) and one ring for the remainder; per_launch
+    passes per kernel launch (0: the library's choice)."""
     sizes = [per_ring] * (steps // per_ring) + ([steps % per_ring] if steps % per_ring else [])
     rings = []
     for i, n in enumerate(sizes):
         rot = (i * per_ring) % len(bs)
         order = list(range(rot, len(bs))) + list(range(rot))
         nb = min(n, len(bs))
-        st, ring = svt.svt_ring_create(ctx, [bs[j] for j in order[:nb]], [rs[j] for j in order[:nb]], n)
+        st, ring = svt.svt_ring_create(ctx, [bs[j] for j in order[:nb]], [rs[j] for j in order[:nb]],
+                                       n, per_launch)
         svt.check(st, "svt_ring_create")
         rings.append((ring, n))
     return rings
@@ -198,8 +200,11 @@ def section_fit(args, svt, synth, torch):
     rs = [r.struct() for r in results]
     stream = torch.cuda.current_stream().cuda_stream
     per_ring = max(1, min(args.ring_passes, args.steps))
-    warm = make_rings(svt, ctx.handle, bs, rs, max(1, args.warmup), per_ring)
-    timed = make_rings(svt, ctx.handle, bs, rs, args.steps, per_ring)
+    warm = make_rings(svt, ctx.handle, bs, rs, max(1, args.warmup), per_ring, args.passes_per_launch)
+    timed = make_rings(svt, ctx.handle, bs, rs, args.steps, per_ring, args.passes_per_launch)
+    shapes = [svt.svt_ring_info(r) for r, _ in timed]
+    per_launch = shapes[0][1]
+    launches = sum(x[2] for x in shapes)
     run_rings(svt, ctx.handle, warm, stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -209,11 +214,13 @@ def section_fit(args, svt, synth, torch):
     for ring, _ in warm + timed:
         svt.svt_ring_destroy(ring)
     passes = args.steps
-    kernel_s = sum(dev) * 1e-9 / passes
+    kernel_s = sum(dev) * 1e-9 / passes          # per pass
+    launch_s = sum(dev) * 1e-9 / launches        # per kernel launch
     # a longer run of the same rings' shape for the steady-state check
     requests = section_fit_requests(args, svt, ctx, bs, rs, torch)
     alg = algorithmic_bytes(batch.n_events, batch.n_roads, batch.n_hits)
-    achieved = alg / kernel_s / 1e9
+    # one launch covers passes / launches passes of alg bytes each
+    achieved = alg * passes / launches / launch_s / 1e9
     out = dict(
         value=total / elapsed, ms_per_step=elapsed * 1e3 / passes,
         combinations=int(total // passes),
@@ -221,18 +228,20 @@ def section_fit(args, svt, synth, torch):
                             "72 sectors, lattice constants, half the roads with a planted track",
                 "step": "one pass of the fit over the batch; the timed passes run back to back "
                         f"as graph launches of up to {per_ring} passes over {args.copies} "
-                        "rotating input copies",
+                        f"rotating input copies, {per_launch} passes per kernel launch",
                 "n_events": batch.n_events, "n_roads": batch.n_roads, "n_hits": batch.n_hits,
                 "combinations": int(total // passes), "chi2_cut": consts.chi2_cut,
                 "device": info["arch"], "compute_units": info["compute_units"],
-                "tuning": ctx.tuning(), "input_copies": args.copies, "ring_passes": per_ring},
+                "tuning": ctx.tuning(), "input_copies": args.copies, "ring_passes": per_ring,
+                "passes_per_launch": per_launch},
         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                  "kernel_us": kernel_s * 1e6, "algorithmic_bytes": alg,
-                  "timed_launches": passes,
+                  "kernel_us": launch_s * 1e6, "kernel_us_per_pass": kernel_s * 1e6,
+                  "algorithmic_bytes": alg * passes // launches, "algorithmic_bytes_per_pass": alg,
+                  "passes_per_launch": per_launch, "timed_launches": launches,
                   "kernel_us_basis": "device time of the timed graph launches (events around each "
-                                     "launch on its stream) / passes: back-to-back fit kernels on "
-                                     "one stream, the gaps between them included"},
+                                     "graph launch on its stream) / kernel launches: back-to-back "
+                                     "fit kernels on one stream, the gaps between them included"},
         requests=requests, batch=batch, consts=consts)
     ctx.close()
     return out
@@ -667,6 +676,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--copies", type=int, default=32)
+    ap.add_argument("--passes-per-launch", type=int, default=0,
+                    help="fit passes per kernel launch in the rings (0: the library's choice)")
     ap.add_argument("--ring-passes", type=int, default=100,
                     help="passes per captured graph launch in the timed region")
     ap.add_argument("--fit-streams", type=int, default=2,

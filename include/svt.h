@@ -365,8 +365,14 @@ svt_status svt_plan_fit(svt_plan *plan, const svt_event_batch *batch, const svt_
  * (svt_ring_run returns SVT_E_STATE).  Destroy rings before their context.
  * ------------------------------------------------------------------------ */
 typedef struct svt_ring svt_ring;
+/* passes_per_launch: passes one kernel launch of the block kernel covers
+ * (each of its batches spread over the same number of blocks), 1..64, or 0
+ * for automatic (about eight full grids' worth of blocks, at most 8 passes);
+ * the wavefront kernel takes one pass per launch.  Results do not depend on
+ * it. */
 svt_status svt_ring_create(svt_ctx *ctx, int32_t n_batches, const svt_event_batch *batches,
-                           const svt_results *results, int32_t n_passes, svt_ring **out);
+                           const svt_results *results, int32_t n_passes, int32_t passes_per_launch,
+                           svt_ring **out);
 /* Replay the ring's graph on hip_stream (asynchronous; one run per ring in
  * flight, else SVT_E_AGAIN).  svt_result on the ring's context then gives the
  * sums over all passes (total_comb = sum over passes of each pass's
@@ -374,6 +380,10 @@ svt_status svt_ring_create(svt_ctx *ctx, int32_t n_batches, const svt_event_batc
  * reported (each the index within that pass's batch) and device_ns from the
  * first pass to the last. */
 svt_status svt_ring_run(svt_ring *ring, void *hip_stream, svt_ticket *ticket);
+/* The ring's shape: its passes, the passes one kernel launch covers and the
+ * launches per run (any pointer may be NULL). */
+svt_status svt_ring_info(const svt_ring *ring, int32_t *n_passes, int32_t *passes_per_launch,
+                         int32_t *n_launches);
 /* Waits for the ring's run in flight, if any, then frees it. */
 svt_status svt_ring_destroy(svt_ring *ring);
 

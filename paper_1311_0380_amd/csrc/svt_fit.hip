@@ -208,6 +208,17 @@ __device__ __forceinline__ void run_rows(Row &st, const int16_t *hit, uint32_t p
     }
 }
 
+// The launch arguments through a pointer the compiler cannot see through, so
+// that their loads are repeated where the fields are used rather than hoisted
+// to the kernel's start and held (or spilled) in scalar registers throughout.
+typedef const __attribute__((address_space(4))) FitArgs ConstArgs;
+__device__ __forceinline__ const FitArgs &fresh_args(const FitArgs &a)
+{
+    ConstArgs *p = (ConstArgs *)&a;
+    asm volatile("" : "+s"(p));
+    return *(const FitArgs *)p;
+}
+
 // Hit words a in [0, 4096): no bit of 15..12 set in either half of a word pair.
 __device__ __forceinline__ bool words_ok(uint32_t pair) { return (pair & 0xF000F000u) == 0u; }
 
@@ -218,10 +229,11 @@ __device__ __forceinline__ bool words_ok(uint32_t pair) { return (pair & 0xF000F
 // image into LDS, issued after its own loads so that the two latencies
 // overlap (the image is first read after the sub-chunk's first barrier).
 template <bool F>
-__device__ int process_sub(const FitArgs &a, Shared &S, double *s_cd, int32_t s, int32_t rb,
+__device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t s, int32_t rb,
                            int32_t n_roads, int32_t n_hits, int32_t n_sectors, int32_t ne,
                            double cut, bool vec, bool copy_image, Acc &acc)
 {
+    const FitArgs &a = fresh_args(a_in);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     const int32_t r = s + tid;
@@ -554,24 +566,29 @@ __device__ __forceinline__ int32_t first_event_at(const int32_t *road_offsets, i
 // Static schedules (no shared counter): 1 = cyclic (chunk c -> block c mod
 // grid), 2 = blocked (block b owns a contiguous range of chunks); schedule 3
 // (balanced by roads) is set up in the kernel.
-__device__ __forceinline__ void chunk_range(int32_t n_chunks, int32_t schedule, int32_t &first,
-                                            int32_t &step, int32_t &last)
+__device__ __forceinline__ void chunk_range(int32_t n_chunks, int32_t schedule, int32_t blk,
+                                            int32_t nblk, int32_t &first, int32_t &step,
+                                            int32_t &last)
 {
     if (schedule == 2) {
-        const int64_t g = gridDim.x, b = blockIdx.x;
+        const int64_t g = nblk, b = blk;
         first = (int32_t)((int64_t)n_chunks * b / g);
         last = (int32_t)((int64_t)n_chunks * (b + 1) / g);
         step = 1;
     } else {
-        first = blockIdx.x;
+        first = blk;
         last = n_chunks;
-        step = gridDim.x;
+        step = nblk;
     }
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-fit_kernel(FitArgs a)
+// One block's share of one batch: block blk of the nblk blocks the batch is
+// spread over.  staged: the sector constants image is in LDS already (a
+// block fitting several batches stages it once); set once it is.
+__device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk, const int32_t nblk,
+                                          bool &staged)
 {
+    const FitArgs &a = fresh_args(a_in);
     extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ __align__(16) Shared S;
     const int tid = threadIdx.x;
@@ -605,7 +622,7 @@ fit_kernel(FitArgs a)
         // some block whatever the partition, so that malformed offsets cannot
         // escape the check
         const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
-        const int64_t G = gridDim.x, b = blockIdx.x;
+        const int64_t G = nblk, b = blk;
         uint32_t bad_event = 0xFFFFFFFFu;
         if (wid < 2) {
             const int64_t bb = b + wid;
@@ -621,7 +638,8 @@ fit_kernel(FitArgs a)
                                  (e == n_events - 1 && hi != n_roads);
                 if (bad) bad_event = min(bad_event, (uint32_t)e);
             }
-            for (int i = t2; i < n16; i += 128) cdst[i] = csrc[i];
+            if (!staged)
+                for (int i = t2; i < n16; i += 128) cdst[i] = csrc[i];
         }
         acc.err_event = min(acc.err_event, wave_min(bad_event));
         __syncthreads();
@@ -633,7 +651,7 @@ fit_kernel(FitArgs a)
         __syncthreads();   // S.misc is reused by the sub-chunks
     } else {
         const int32_t n_chunks = n_events > 0 ? (n_events + E - 1) / E : 0;
-        chunk_range(n_chunks, a.schedule, c_first, c_step, c_last);
+        chunk_range(n_chunks, a.schedule, blk, nblk, c_first, c_step, c_last);
     }
 
     // the first chunk's event boundaries are in flight while the sector
@@ -647,7 +665,8 @@ fit_kernel(FitArgs a)
 
     // (with the cyclic and blocked schedules the first sub-chunk stages the
     // sector constants, see process_sub)
-    bool copy_image = a.schedule != 3;
+    if (a.schedule == 3) staged = true;
+    bool copy_image = !staged;
     static_assert(kBins == kBlock, "one bin per thread");
     S.bin[tid] = 0;
     if (tid == 0) S.misc[2] = 0;
@@ -683,6 +702,7 @@ fit_kernel(FitArgs a)
         acc.err_event = min(acc.err_event, wave_min(bad_event));
         __syncthreads();
     }
+    staged = !copy_image;
 
     // block sums -> host-mapped partials (the host reduces them); the
     // wavefront sums are uniform already.  Lane and wave ids are recomputed
@@ -703,8 +723,33 @@ fit_kernel(FitArgs a)
             p.err_event = min(p.err_event, s_part[w].err_event);
         }
         p.seq = request_seq(a);
-        a.partials[blockIdx.x] = p;
+        a.partials[blk] = p;
     }
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+fit_kernel(FitArgs a)
+{
+    // the argument is read in place, in the kernel argument segment (where
+    // it is the first argument): its address must not escape, or it would be
+    // copied to private memory
+    (void)a;
+    ConstArgs *pa = (ConstArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    bool staged = false;
+    fit_block(*(const FitArgs *)pa, (int32_t)blockIdx.x, (int32_t)gridDim.x, staged);
+}
+
+// Several batches in one launch: batch i takes blocks [i per, (i + 1) per),
+// so that blocks of later batches start wherever blocks of earlier ones end.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+fit_kernel_multi(const FitArgs *__restrict__ args, int32_t per)
+{
+    const int32_t i = (int32_t)blockIdx.x / per;
+    // read through the constant address space: the argument loads can then be
+    // repeated where they are used instead of holding every field in registers
+    ConstArgs *ca = (ConstArgs *)args;
+    bool staged = false;
+    fit_block(*(const FitArgs *)&ca[i], (int32_t)blockIdx.x - i * per, per, staged);
 }
 
 // ---------------------------------------------------------------------------
@@ -779,8 +824,20 @@ __global__ void copy_seq(const uint32_t *src, uint32_t *dst)
 hipError_t prepare_fit()
 {
     const int max_dyn = 256 * kCstBytesPerSector;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel_multi),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
+    return e;
+}
+
+hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, size_t dyn_lds,
+                            hipStream_t stream)
+{
+    hipLaunchKernelGGL(fit_kernel_multi, dim3(n_batches * per), dim3(kBlock), dyn_lds, stream, args,
+                       (int32_t)per);
+    return hipGetLastError();
 }
 
 hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream,

@@ -92,7 +92,7 @@ struct FitArgs {
     int32_t events_per_chunk;
     int32_t schedule;           // 1 cyclic, 2 blocked
     // request bookkeeping
-    BlockPartial *partials;     // host-mapped, [gridDim.x]
+    BlockPartial *partials;     // host-mapped, one per block the batch is spread over
     uint32_t seq;
 };
 
@@ -114,6 +114,10 @@ hipError_t prepare_fit();   // one-time kernel attributes (call outside graph ca
 // (no separate event packets on the stream).
 hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream,
                       hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// n_batches batches in one launch of the block kernel: args is device memory
+// holding one FitArgs per batch; batch i is spread over blocks [i per, (i+1) per).
+hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, size_t dyn_lds,
+                            hipStream_t stream);
 hipError_t prepare_fit_wave();
 hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream,
                            hipEvent_t start = nullptr, hipEvent_t stop = nullptr);

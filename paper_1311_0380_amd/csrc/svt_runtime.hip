@@ -149,10 +149,13 @@ struct svt_plan {
 struct svt_ring {
     svt_ctx *ctx = nullptr;
     int32_t n_batches = 0, n_passes = 0;
+    int32_t per_launch = 1;                 // passes per kernel launch
     int total_parts = 0;                    // block partials of all passes
     svt::BlockPartial *partials = nullptr;  // host-mapped [total_parts], pass after pass
     uint32_t *seq_host = nullptr;           // host-mapped: the run's ticket
     uint32_t *seq_dev = nullptr;            // device copy the fit kernels read
+    svt::FitArgs *args_dev = nullptr;       // device: the launch arguments of every pass
+    size_t args_bytes = 0;
     uint64_t const_gen = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -343,8 +346,8 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
     return ls;
 }
 
-hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &ls,
-                         hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr)
+// The launch arguments that follow from the context's tables and the shape.
+void set_shape_args(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &ls)
 {
     const char *w = static_cast<const char *>(c->cst_wave);
     a.cst_pb = reinterpret_cast<const double *>(w);
@@ -354,6 +357,12 @@ hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &l
     a.frac_key = c->cut < (1ull << 44) ? 1 : 0;
     a.cst_block = static_cast<const double *>(c->cst_block);
     a.events_per_chunk = ls.epc;
+}
+
+hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &ls,
+                         hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr)
+{
+    set_shape_args(c, a, ls);
     if (ls.kernel == 2) return svt::launch_fit_wave(a, ls.grid, st, start, stop);
     return svt::launch_fit(a, ls.grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st, start,
                            stop);
@@ -1389,18 +1398,21 @@ static void ring_free(svt_ring *r)
     if (r->exec) (void)hipGraphExecDestroy(r->exec);
     if (r->graph) (void)hipGraphDestroy(r->graph);
     if (r->seq_dev) dev_free(r->ctx, r->seq_dev, 256);
+    if (r->args_dev) dev_free(r->ctx, r->args_dev, r->args_bytes);
     if (r->seq_host) (void)hipHostFree(r->seq_host);
     if (r->partials) (void)hipHostFree(r->partials);
     delete r;
 }
 
 svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch *batches,
-                           const svt_results *results, int32_t n_passes, svt_ring **out)
+                           const svt_results *results, int32_t n_passes, int32_t passes_per_launch,
+                           svt_ring **out)
 {
     if (c == nullptr || out == nullptr || batches == nullptr || results == nullptr)
         return SVT_E_INVAL;
     *out = nullptr;
-    if (n_passes < 1 || n_passes > 1024 || n_batches < 1 || n_batches > n_passes)
+    if (n_passes < 1 || n_passes > 1024 || n_batches < 1 || n_batches > n_passes ||
+        passes_per_launch < 0 || passes_per_launch > 64)
         return SVT_E_INVAL;
     for (int i = 0; i < n_batches; ++i) {
         const svt_status vs = check_call(&batches[i], &results[i]);
@@ -1418,11 +1430,37 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     r->n_passes = n_passes;
     r->const_gen = c->const_gen;
     std::vector<LaunchShape> shapes(n_batches);
-    std::vector<int> part_off(n_passes + 1, 0);
-    for (int i = 0; i < n_batches; ++i)
+    int max_grid = 1;
+    for (int i = 0; i < n_batches; ++i) {
         shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads,
                                  batches[i].n_hits, false);
-    for (int p = 0; p < n_passes; ++p) part_off[p + 1] = part_off[p] + shapes[p % n_batches].grid;
+        max_grid = shapes[i].grid > max_grid ? shapes[i].grid : max_grid;
+    }
+    // passes per launch: the block kernel takes several batches per launch
+    // (about eight full grids' worth of blocks, at most 8 batches), which
+    // spreads the launch's start and its last blocks over several batches
+    int k = passes_per_launch;
+    if (c->tuning.kernel == 2) k = 1;
+    if (k == 0) {
+        const int64_t want = 8 * (int64_t)c->cu_count * 3;
+        k = (int)((want + max_grid - 1) / max_grid);
+        if (k > 8) k = 8;
+    }
+    if (k < 1) k = 1;
+    if (k > n_passes) k = n_passes;
+    r->per_launch = k;
+    // each launch of the block kernel gives every batch the same number of
+    // blocks (the largest grid of its passes); block partials pass by pass
+    const int n_launch = (n_passes + k - 1) / k;
+    std::vector<int> launch_per(n_launch, 1), part_off(n_passes + 1, 0);
+    for (int l = 0; l < n_launch; ++l) {
+        for (int p = l * k; p < n_passes && p < (l + 1) * k; ++p) {
+            const int gp = shapes[p % n_batches].grid;
+            launch_per[l] = gp > launch_per[l] ? gp : launch_per[l];
+        }
+    }
+    for (int p = 0; p < n_passes; ++p)
+        part_off[p + 1] = part_off[p] + (k > 1 ? launch_per[p / k] : shapes[p % n_batches].grid);
     r->total_parts = part_off[n_passes];
     svt_status st = dev_alloc(c, reinterpret_cast<void **>(&r->seq_dev), 256);
     if (st != SVT_OK) {
@@ -1445,41 +1483,63 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     const uint32_t *seq_src =
         static_cast<const uint32_t *>(device_view(r->seq_host, SVT_MEM_MAPPED));
 
-    // the graph: the run's ticket into device memory, then the passes in order
+    // the launch arguments of every pass
+    std::vector<svt::FitArgs> args(n_passes);
+    for (int p = 0; p < n_passes; ++p) {
+        const svt_event_batch &b = batches[p % n_batches];
+        const svt_results &res = results[p % n_batches];
+        svt::FitArgs &a = args[p];
+        memset(&a, 0, sizeof a);
+        a.road_offsets = b.road_offsets;
+        a.sector = b.sector;
+        a.nhits4 = reinterpret_cast<const uint32_t *>(b.nhits);
+        a.hit_offsets = b.hit_offsets;
+        a.hits = b.hits;
+        a.xft2 = reinterpret_cast<const uint32_t *>(b.xft);
+        a.n_events = b.n_events;
+        a.n_roads = b.n_roads;
+        a.n_hits = b.n_hits;
+        a.n_sectors = c->n_sectors;
+        a.coef = c->coef;
+        a.offset = c->offset;
+        a.cut_d = (double)c->cut;
+        a.ncomb = res.ncomb;
+        a.npass = res.npass;
+        a.best = res.best;
+        a.chi2 = res.chi2;
+        a.params = res.params;
+        a.hit_index4 = reinterpret_cast<uint32_t *>(res.hit_index);
+        a.ntracks = res.ntracks;
+        a.schedule = c->tuning.schedule;
+        a.partials = parts_dev + part_off[p];
+        a.seq_dev = r->seq_dev;
+        set_shape_args(c, a, shapes[p % n_batches]);
+    }
+    if (k > 1) {
+        r->args_bytes = sizeof(svt::FitArgs) * (size_t)n_passes;
+        st = dev_alloc(c, reinterpret_cast<void **>(&r->args_dev), r->args_bytes);
+        if (st == SVT_OK && hipMemcpy(r->args_dev, args.data(), r->args_bytes,
+                                      hipMemcpyHostToDevice) != hipSuccess)
+            st = hip_fail(hipGetLastError(), "ring arguments");
+        if (st != SVT_OK) {
+            ring_free(r);
+            return st;
+        }
+    }
+
+    // the graph: the run's ticket into device memory, then the launches in order
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t e2 = svt::launch_copy_seq(seq_src, r->seq_dev, cs);
-        for (int p = 0; p < n_passes && e2 == hipSuccess; ++p) {
-            const svt_event_batch &b = batches[p % n_batches];
-            const svt_results &res = results[p % n_batches];
-            svt::FitArgs a;
-            memset(&a, 0, sizeof a);
-            a.road_offsets = b.road_offsets;
-            a.sector = b.sector;
-            a.nhits4 = reinterpret_cast<const uint32_t *>(b.nhits);
-            a.hit_offsets = b.hit_offsets;
-            a.hits = b.hits;
-            a.xft2 = reinterpret_cast<const uint32_t *>(b.xft);
-            a.n_events = b.n_events;
-            a.n_roads = b.n_roads;
-            a.n_hits = b.n_hits;
-            a.n_sectors = c->n_sectors;
-            a.coef = c->coef;
-            a.offset = c->offset;
-            a.cut_d = (double)c->cut;
-            a.ncomb = res.ncomb;
-            a.npass = res.npass;
-            a.best = res.best;
-            a.chi2 = res.chi2;
-            a.params = res.params;
-            a.hit_index4 = reinterpret_cast<uint32_t *>(res.hit_index);
-            a.ntracks = res.ntracks;
-            a.schedule = c->tuning.schedule;
-            a.partials = parts_dev + part_off[p];
-            a.seq_dev = r->seq_dev;
-            e2 = launch_shaped(c, a, shapes[p % n_batches], cs);
+        for (int l = 0; l < n_launch && e2 == hipSuccess; ++l) {
+            const int p0 = l * k, np = (p0 + k <= n_passes) ? k : n_passes - p0;
+            if (k > 1)
+                e2 = svt::launch_fit_multi(r->args_dev + p0, np, launch_per[l],
+                                           (size_t)c->n_sectors * svt::kCstBytesPerSector, cs);
+            else
+                e2 = launch_shaped(c, args[p0], shapes[p0 % n_batches], cs);
         }
         e = hipStreamEndCapture(cs, &r->graph);
         if (e == hipSuccess && e2 != hipSuccess) e = e2;
@@ -1524,6 +1584,16 @@ svt_status svt_ring_run(svt_ring *r, void *hip_stream, svt_ticket *ticket)
     s.ring = r;
     r->busy = true;
     *ticket = s.ticket;
+    return SVT_OK;
+}
+
+svt_status svt_ring_info(const svt_ring *r, int32_t *n_passes, int32_t *passes_per_launch,
+                         int32_t *n_launches)
+{
+    if (r == nullptr) return SVT_E_INVAL;
+    if (n_passes) *n_passes = r->n_passes;
+    if (passes_per_launch) *passes_per_launch = r->per_launch;
+    if (n_launches) *n_launches = (r->n_passes + r->per_launch - 1) / r->per_launch;
     return SVT_OK;
 }
 

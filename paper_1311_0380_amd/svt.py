@@ -108,9 +108,12 @@ SIGNATURES = {
     "svt_plan_fit": (ctypes.c_int32, [P, ctypes.POINTER(svt_event_batch),
                                       ctypes.POINTER(svt_results), P,
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "svt_ring_info": (ctypes.c_int32, [P, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     "svt_ring_create": (ctypes.c_int32, [P, ctypes.c_int32, ctypes.POINTER(svt_event_batch),
                                          ctypes.POINTER(svt_results), ctypes.c_int32,
-                                         ctypes.POINTER(P)]),
+                                         ctypes.c_int32, ctypes.POINTER(P)]),
     "svt_ring_run": (ctypes.c_int32, [P, P, ctypes.POINTER(ctypes.c_int64)]),
     "svt_ring_destroy": (ctypes.c_int32, [P]),
     "svt_shadow_slices": (ctypes.c_int32, [ctypes.c_int32, ctypes.c_int32,
@@ -325,14 +328,22 @@ def svt_plan_buffers(plan):
     return b, r
 
 
-def svt_ring_create(ctx, batches, results, n_passes):
+def svt_ring_info(ring):
+    """(n_passes, passes_per_launch, n_launches) of a ring."""
+    v = [ctypes.c_int32(0) for _ in range(3)]
+    check(lib.svt_ring_info(ring, *[ctypes.byref(x) for x in v]), "svt_ring_info")
+    return tuple(x.value for x in v)
+
+
+def svt_ring_create(ctx, batches, results, n_passes, passes_per_launch=0):
     """A ring over device batches / results (lists of svt_event_batch and
     svt_results of equal length); returns (status, ring handle or None)."""
     n = len(batches)
     ba = (svt_event_batch * n)(*batches)
     ra = (svt_results * n)(*results)
     h = P()
-    st = lib.svt_ring_create(ctx, n, ba, ra, int(n_passes), ctypes.byref(h))
+    st = lib.svt_ring_create(ctx, n, ba, ra, int(n_passes), int(passes_per_launch),
+                             ctypes.byref(h))
     return st, (h if st == SVT_OK else None)
 
 

@@ -18,7 +18,8 @@ def env():
     svt.svt_destroy(ctx)
 
 
-def test_ring_passes_match_the_oracle(env, oracle_lib):
+@pytest.mark.parametrize("per_launch", [1, 3, 0, 7])
+def test_ring_passes_match_the_oracle(env, oracle_lib, per_launch):
     svt, ctx = env
     import torch
     # three different batches (sizes differ, so grids differ per pass)
@@ -31,9 +32,15 @@ def test_ring_passes_match_the_oracle(env, oracle_lib):
     svt.check(svt.svt_load_constants(ctx, consts.coef, consts.offset, consts.chi2_cut))
     dbs = [svt.to_device(b) for b in batches]
     drs = [svt.DeviceResults(b.n_events, b.n_roads) for b in batches]
-    st, ring = svt.svt_ring_create(ctx, [d.struct() for d in dbs], [r.struct() for r in drs], 7)
+    st, ring = svt.svt_ring_create(ctx, [d.struct() for d in dbs], [r.struct() for r in drs], 7,
+                                   per_launch)
     svt.check(st, "svt_ring_create")
     try:
+        n_passes, k, n_launch = svt.svt_ring_info(ring)
+        assert n_passes == 7 and n_launch == (7 + k - 1) // k
+        if per_launch:
+            assert k == per_launch
+        print(f"ring: 7 passes, {k} per launch", flush=True)
         wants, tot = [], dict(total_comb=0, total_pass=0, total_tracks=0)
         for b in batches:
             rc, w, s = oracle_lib.fit_batch(b, consts, n_threads=8)
@@ -79,6 +86,8 @@ def test_ring_rules(env):
     assert svt.svt_ring_create(ctx, [bs], [co.struct()], 2)[0] == svt.SVT_E_INVAL
     assert svt.svt_ring_create(ctx, [bs], [rs], 0)[0] == svt.SVT_E_INVAL
     assert svt.svt_ring_create(ctx, [bs, bs], [rs, rs], 1)[0] == svt.SVT_E_INVAL
+    assert svt.svt_ring_create(ctx, [bs], [rs], 2, -1)[0] == svt.SVT_E_INVAL
+    assert svt.svt_ring_create(ctx, [bs], [rs], 2, 65)[0] == svt.SVT_E_INVAL
     st, ring = svt.svt_ring_create(ctx, [bs], [rs], 3)
     svt.check(st)
     try:
