@@ -78,7 +78,7 @@ struct Acc {
 };
 
 struct Shared {
-    double base[3][kSubRoads];              // b + A[:,4] x4 + A[:,5] x5, rows 3..5
+    int32_t base[3][kSubRoads];             // b + A[:,4] x4 + A[:,5] x5, rows 3..5 (exact in int32)
     // per road, what its rows need (indices into the hit window and into
     // the constants image, in doubles):
     //   x  first hit of row layer c | of d << 16
@@ -95,13 +95,19 @@ struct Shared {
     uint32_t row[kRowCap];
     __align__(16) int16_t hit[kHitCap + 16];   // staged hit window (+ pad read by row loops)
     __align__(16) uint32_t bin[kBins];
-    int32_t evro[kMaxEventsPerChunk + 1];
+    int32_t evro[kMaxEventsPerChunk + 1];   // event road offsets of the chunk
     uint32_t evcnt[kMaxEventsPerChunk];
     uint32_t wrows[kWaves];                 // rows of each wavefront's roads
     uint32_t wout[kWaves];                  // first lane of each wavefront outside the window
     uint32_t wfit[kWaves];                  // first lane of each wavefront that does not fit
     int32_t misc[4];                        // [2]: a staged word is out of range; [3]: rows
 };
+
+// LDS per block: the static part plus the constants image (272 bytes per
+// sector).  Three blocks (twelve wavefronts, the VGPR limit) share a CU's
+// 160 KB up to 72 sectors; LDS is allocated in 512-byte granules.
+static_assert(((sizeof(Shared) + 1024 + 72 * kCstBytesPerSector + 511) / 512) * 512 * 3 <= 160 * 1024,
+              "three blocks per CU at 72 sectors");
 
 // OR across the wavefront (all lanes active), as a uniform value.
 __device__ __forceinline__ uint32_t wave_or(uint32_t x)
@@ -214,81 +220,113 @@ __device__ __forceinline__ void run_rows(Row &st, const int16_t *hit, uint32_t p
 typedef const __attribute__((address_space(4))) FitArgs ConstArgs;
 __device__ __forceinline__ const FitArgs &fresh_args(const FitArgs &a)
 {
-    ConstArgs *p = (ConstArgs *)&a;
-    asm volatile("" : "+s"(p));
-    return *(const FitArgs *)p;
+    // (the address is uniform; readfirstlane keeps it in scalar registers
+    // wherever the compiler cannot tell)
+    const uint64_t v = reinterpret_cast<uint64_t>((ConstArgs *)&a);
+    uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v) |
+                 ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32);
+    asm volatile("" : "+s"(u));
+    return *(const FitArgs *)reinterpret_cast<ConstArgs *>(u);
 }
 
 // Hit words a in [0, 4096): no bit of 15..12 set in either half of a word pair.
 __device__ __forceinline__ bool words_ok(uint32_t pair) { return (pair & 0xF000F000u) == 0u; }
 
-// Process the roads [s, rb) of the current chunk starting at road s; returns
-// how many roads were fitted (at least one when s < rb).
-//
-// copy_image: the block's first sub-chunk also stages the sector constants
-// image into LDS, issued after its own loads so that the two latencies
-// overlap (the image is first read after the sub-chunk's first barrier).
-template <bool F>
-__device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t s, int32_t rb,
-                           int32_t n_roads, int32_t n_hits, int32_t n_sectors, int32_t ne,
-                           double cut, bool vec, bool copy_image, Acc &acc)
-{
-    const FitArgs &a = fresh_args(a_in);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wid = tid >> 6;
-    const int32_t r = s + tid;
-    const bool inr = r < rb;
-
-    // The hit window of the sub-chunk: from the first road's first hit,
-    // rounded down to a 16-byte boundary, to the end of the last road the
-    // sub-chunk can hold (at least the first road's end), at most kHitCap
-    // words.  A road inside the window finds its hits at their offset from
-    // the window's start.
-    const int32_t s_end = min(rb, s + kSubRoads);
-    const int32_t hs = clampi(a.hit_offsets[s], 0, n_hits);
-    const int32_t hw = hs & ~7;
-    const int32_t he = clampi(max(a.hit_offsets[s_end], a.hit_offsets[s + 1]), hs, n_hits);
-    const int32_t W = min(he - hw, kHitCap);
-
-    // one round of loads: each thread's road and its share of the window
-    uint32_t sec = 0, nh4 = 0, x2 = 0;
-    int32_t h0 = 0, h1 = 0;
-    if (inr) {
-        sec = a.sector[r];
-        nh4 = a.nhits4[r];
-        h0 = a.hit_offsets[r];
-        h1 = a.hit_offsets[r + 1];
-        x2 = a.xft2[r];
-    }
+// One sub-chunk's inputs, loaded ahead of their use: the words of the road
+// of each thread and the thread's share of the hit window.
+struct SubIn {
+    uint32_t sec, nh4, x2;
+    int32_t h0, h1;
     uint4 hv[kVecsPerThread];
+};
+
+// The hit window of the sub-chunk that starts at road s of a chunk ending at
+// road rb: from the first road's first hit, rounded down to a 16-byte
+// boundary, to the end of the last road the sub-chunk can hold (at least the
+// first road's end), at most kHitCap words.  A road inside the window finds
+// its hits at their offset from the window's start.  window_loads issues the
+// three offsets it needs, one per lane (lanes 0, 1 and 2 of the result), so
+// that nothing waits for them before window_of reads them.
+__device__ __forceinline__ int32_t window_loads(const FitArgs &a, int32_t s, int32_t rb)
+{
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int32_t s_end = min(rb, s + kSubRoads);
+    return a.hit_offsets[lane == 1 ? s_end : (lane == 2 ? s + 1 : s)];
+}
+
+__device__ __forceinline__ void window_of(int32_t raw, int32_t n_hits, int32_t &hw, int32_t &W)
+{
+    const int32_t hs = clampi(__builtin_amdgcn_readlane(raw, 0), 0, n_hits);
+    const int32_t he = max(__builtin_amdgcn_readlane(raw, 1), __builtin_amdgcn_readlane(raw, 2));
+    hw = hs & ~7;
+    W = min(clampi(he, hs, n_hits) - hw, kHitCap);
+}
+
+// The words of road s + tid (zeros past rb).
+__device__ __forceinline__ void road_loads(const FitArgs &a, int32_t s, int32_t rb, SubIn &in)
+{
+    const int32_t r = s + (int32_t)threadIdx.x;
+    in.sec = 0;
+    in.nh4 = 0;
+    in.x2 = 0;
+    in.h0 = 0;
+    in.h1 = 0;
+    if (r < rb) {
+        in.sec = a.sector[r];
+        in.nh4 = a.nhits4[r];
+        in.h0 = a.hit_offsets[r];
+        in.h1 = a.hit_offsets[r + 1];
+        in.x2 = a.xft2[r];
+    }
+}
+
+// The thread's 16-byte groups of the window [hw, hw + W) (zeros past it).
+__device__ __forceinline__ void window_loads_hits(const FitArgs &a, int32_t hw, int32_t W, int32_t n_hits,
+                                                  bool vec, SubIn &in)
+{
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < kVecsPerThread; ++q) {
         int32_t t = 8 * (tid + q * kBlock);
         // recomputed per sub-chunk: a per-lane address hoisted out of the
         // chunk loop would stay live across the row loops
         asm volatile("" : "+v"(t));
-        hv[q] = make_uint4(0u, 0u, 0u, 0u);
+        in.hv[q] = make_uint4(0u, 0u, 0u, 0u);
         if (vec && t + 8 <= W) {
-            hv[q] = *reinterpret_cast<const uint4 *>(a.hits + hw + t);
+            in.hv[q] = *reinterpret_cast<const uint4 *>(a.hits + hw + t);
         } else if (t < W) {
             // the window's last, partial group (or a hits array that is not
-            // 16-byte aligned): word by word, zeros past the window
-            uint64_t lo = 0, hi = 0;
-            for (int i = 0; i < 8 && t + i < W; ++i) {
-                const uint64_t v = (uint16_t)a.hits[hw + t + i];
-                if (i < 4) lo |= v << (16 * i);
-                else hi |= v << (16 * (i - 4));
-            }
-            hv[q] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+            // 16-byte aligned): word by word, all eight loads in flight at
+            // once (indices clamped into the array, which holds at least the
+            // window), zeros past the window
+            uint32_t w[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w[i] = (uint16_t)a.hits[min(hw + t + i, n_hits - 1)];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w[i] = t + i < W ? w[i] : 0u;
+            in.hv[q] = make_uint4(w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16),
+                                  w[6] | (w[7] << 16));
         }
     }
-    if (copy_image) {
-        const uint4 *csrc = reinterpret_cast<const uint4 *>(a.cst_block);
-        uint4 *cdst = reinterpret_cast<uint4 *>(s_cd);
-        const int n16 = n_sectors * kCstBytesPerSector / 16;
-        for (int i = tid; i < n16; i += kBlock) cdst[i] = csrc[i];
-    }
+}
 
+// Phase A of the sub-chunk of roads [s, rb) (one thread per road): validate
+// the roads, order their layers, place their rows in the binned row list,
+// stage the window and the per-road records in LDS.  Returns L, the roads
+// that fit (a prefix of the sub-chunk, at least one when s < rb), and the
+// sub-chunk's rows.
+template <bool F>
+__device__ __forceinline__ int sub_a(Shared &S, const double *s_cd, int32_t s, int32_t rb,
+                                     int32_t n_roads, int32_t n_hits, int32_t n_sectors,
+                                     const SubIn &in, int32_t hw, int32_t W, Acc &acc,
+                                     int32_t &total_rows_out)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int32_t r = s + tid;
+    const bool inr = r < rb;
+    const uint32_t sec = in.sec, nh4 = in.nh4, x2 = in.x2;
+    const int32_t h0 = in.h0, h1 = in.h1;
     const uint32_t n0 = nh4 & 255u, n1 = (nh4 >> 8) & 255u, n2 = (nh4 >> 16) & 255u,
                    n3 = nh4 >> 24;
     const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
@@ -326,8 +364,8 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
     for (int q = 0; q < kVecsPerThread; ++q) {
         const int32_t t = 8 * (tid + q * kBlock);
         if (t < W) {
-            *reinterpret_cast<uint4 *>(&S.hit[t]) = hv[q];
-            bad_word |= !words_ok(hv[q].x | hv[q].y | hv[q].z | hv[q].w);
+            *reinterpret_cast<uint4 *>(&S.hit[t]) = in.hv[q];
+            bad_word |= !words_ok(in.hv[q].x | in.hv[q].y | in.hv[q].z | in.hv[q].w);
         }
     }
     if (bad_word) S.misc[2] = 1;
@@ -383,7 +421,8 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
             const int32_t *cbi = reinterpret_cast<const int32_t *>(cs) + kCstIntB;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                S.base[k][tid] = fma(cs[15 + k], (double)xb, fma(cs[12 + k], (double)xa, (double)cbi[k]));
+                S.base[k][tid] =
+                    (int32_t)fma(cs[15 + k], (double)xb, fma(cs[12 + k], (double)xa, (double)cbi[k]));
         }
     }
     __syncthreads();
@@ -429,8 +468,15 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
     __syncthreads();
     S.bin[tid] = 0;   // ready for the next sub-chunk (kBins == kBlock)
     if (tid == 0) S.misc[2] = 0;
+    total_rows_out = total_rows;
+    return L;
+}
 
-    // B: every combination of every row
+// Phase B: every combination of every row (one thread per row).
+template <bool F>
+__device__ __forceinline__ void sub_b(Shared &S, const double *s_cd, int32_t total_rows, double cut)
+{
+    const int tid = threadIdx.x;
     const double lim = F ? cut + 0.5 : cut;
     for (int idx0 = 0; idx0 < total_rows; idx0 += kBlock) {
         if (idx0 + (tid & ~63) >= total_rows) continue;   // whole wavefront idle
@@ -444,9 +490,9 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
         const double *ca = s_cd + (ra.w & 0xFFFFu), *cb = s_cd + (ra.w >> 16);
         const double hc = (double)S.hit[(ra.x & 0xFFFFu) + ic], hd = (double)S.hit[(ra.x >> 16) + id];
         Row st;
-        st.z3 = fma(cd[0], hd, fma(cc[0], hc, S.base[0][j]));
-        st.z4 = fma(cd[1], hd, fma(cc[1], hc, S.base[1][j]));
-        st.z5 = fma(cd[2], hd, fma(cc[2], hc, S.base[2][j]));
+        st.z3 = fma(cd[0], hd, fma(cc[0], hc, (double)S.base[0][j]));
+        st.z4 = fma(cd[1], hd, fma(cc[1], hc, (double)S.base[1][j]));
+        st.z5 = fma(cd[2], hd, fma(cc[2], hc, (double)S.base[2][j]));
         st.a3 = ca[0];
         st.a4 = ca[1];
         st.a5 = ca[2];
@@ -468,10 +514,22 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
         }
     }
     __syncthreads();
+}
 
-    // C: results of each road.  Its counts, first hit and sector come back
-    // from LDS (zero counts for a malformed road give the same outputs
-    // as the road's error path), which keeps phase A's values out of phase B.
+// Phase C: the results of the sub-chunk's fitted roads [s, s + L) (one
+// thread per road) and their tracks counted per event of the chunk (event
+// road offsets evro, ne events).
+__device__ __forceinline__ void sub_c(const FitArgs &a, Shared &S, const double *s_cd, int32_t s,
+                                      int32_t L, int32_t ne, const int32_t *evro, uint32_t x2,
+                                      Acc &acc)
+{
+    const int tid = threadIdx.x;
+    const int32_t r = s + tid;
+    const bool active = tid < L;
+    const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
+    // Each road's counts, first hit and sector come back from LDS (zero
+    // counts for a malformed road give the same outputs as the road's error
+    // path), which keeps phase A's values out of phase B.
     uint32_t my_comb = 0, my_pass = 0, my_track = 0;
     if (active) {
         const uint32_t c4 = S.n4[tid];
@@ -522,7 +580,7 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
             int lo = 0, hi = ne;   // events [lo, hi): largest e with evro[e] <= r
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if (S.evro[mid] <= r) lo = mid; else hi = mid;
+                if (evro[mid] <= r) lo = mid; else hi = mid;
             }
             atomicAdd(&S.evcnt[lo], 1u);
         }
@@ -534,6 +592,37 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
     acc.pass += wave_sum(my_pass);
     acc.tracks += wave_sum(my_track);
     __syncthreads();
+}
+
+// Process the roads [s, rb) of the current chunk starting at road s; returns
+// how many roads were fitted (at least one when s < rb).
+//
+// copy_image: the block's first sub-chunk also stages the sector constants
+// image into LDS, issued after its own loads so that the two latencies
+// overlap (the image is first read after the sub-chunk's first barrier).
+template <bool F>
+__device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t s, int32_t rb,
+                           int32_t n_roads, int32_t n_hits, int32_t n_sectors, int32_t ne,
+                           double cut, bool vec, bool copy_image, Acc &acc)
+{
+    const FitArgs &a = fresh_args(a_in);
+    const int tid = threadIdx.x;
+    int32_t hw, W;
+    const int32_t wraw = window_loads(a, s, rb);
+    SubIn in;
+    road_loads(a, s, rb, in);
+    window_of(wraw, n_hits, hw, W);
+    window_loads_hits(a, hw, W, n_hits, vec, in);
+    if (copy_image) {
+        const uint4 *csrc = reinterpret_cast<const uint4 *>(a.cst_block);
+        uint4 *cdst = reinterpret_cast<uint4 *>(s_cd);
+        const int n16 = n_sectors * kCstBytesPerSector / 16;
+        for (int i = tid; i < n16; i += kBlock) cdst[i] = csrc[i];
+    }
+    int32_t total_rows;
+    const int L = sub_a<F>(S, s_cd, s, rb, n_roads, n_hits, n_sectors, in, hw, W, acc, total_rows);
+    sub_b<F>(S, s_cd, total_rows, cut);
+    sub_c(a, S, s_cd, s, L, ne, S.evro, in.x2, acc);
     return L;
 }
 
@@ -580,6 +669,39 @@ __device__ __forceinline__ void chunk_range(int32_t n_chunks, int32_t schedule, 
         last = n_chunks;
         step = nblk;
     }
+}
+
+// The block's sums of one batch -> its partials[blk] in host-mapped memory
+// (the host reduces them); the wavefront sums are uniform already.  Lane and
+// wave ids are recomputed here rather than kept live across the whole kernel.
+// Every thread calls it (one barrier).
+__device__ __forceinline__ void write_partial(const FitArgs &a, int32_t blk, const Acc &acc)
+{
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
+    __shared__ BlockPartial s_part[kWaves];
+    if (lane == 0)
+        s_part[wid] = BlockPartial{acc.comb, acc.pass, acc.tracks, acc.err_road, acc.err_event, 0};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BlockPartial p = s_part[0];
+        for (int w = 1; w < kWaves; ++w) {
+            p.comb += s_part[w].comb;
+            p.pass += s_part[w].pass;
+            p.tracks += s_part[w].tracks;
+            p.err_road = min(p.err_road, s_part[w].err_road);
+            p.err_event = min(p.err_event, s_part[w].err_event);
+        }
+        p.seq = request_seq(a);
+        a.partials[blk] = p;
+    }
+}
+
+// The partial of a batch the block has no chunk of.
+__device__ __forceinline__ void write_zero_partial(const FitArgs &a, int32_t blk)
+{
+    if (threadIdx.x == 0)
+        a.partials[blk] = BlockPartial{0, 0, 0, 0xFFFFFFFFu, 0xFFFFFFFFu, request_seq(a)};
 }
 
 // One block's share of one batch: block blk of the nblk blocks the batch is
@@ -704,27 +826,7 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     }
     staged = !copy_image;
 
-    // block sums -> host-mapped partials (the host reduces them); the
-    // wavefront sums are uniform already.  Lane and wave ids are recomputed
-    // here rather than kept live across the whole kernel.
-    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-    const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
-    __shared__ BlockPartial s_part[kWaves];
-    if (lane == 0)
-        s_part[wid] = BlockPartial{acc.comb, acc.pass, acc.tracks, acc.err_road, acc.err_event, 0};
-    __syncthreads();
-    if (tid == 0) {
-        BlockPartial p = s_part[0];
-        for (int w = 1; w < kWaves; ++w) {
-            p.comb += s_part[w].comb;
-            p.pass += s_part[w].pass;
-            p.tracks += s_part[w].tracks;
-            p.err_road = min(p.err_road, s_part[w].err_road);
-            p.err_event = min(p.err_event, s_part[w].err_event);
-        }
-        p.seq = request_seq(a);
-        a.partials[blk] = p;
-    }
+    write_partial(a, blk, acc);
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))

@@ -1430,22 +1430,15 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     r->n_passes = n_passes;
     r->const_gen = c->const_gen;
     std::vector<LaunchShape> shapes(n_batches);
-    int max_grid = 1;
-    for (int i = 0; i < n_batches; ++i) {
+    for (int i = 0; i < n_batches; ++i)
         shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads,
                                  batches[i].n_hits, false);
-        max_grid = shapes[i].grid > max_grid ? shapes[i].grid : max_grid;
-    }
     // passes per launch: the block kernel takes several batches per launch
-    // (about eight full grids' worth of blocks, at most 8 batches), which
-    // spreads the launch's start and its last blocks over several batches
+    // (by default 32), which spreads the launch's start and its last blocks
+    // over many batches; the wavefront kernel takes one
     int k = passes_per_launch;
     if (c->tuning.kernel == 2) k = 1;
-    if (k == 0) {
-        const int64_t want = 8 * (int64_t)c->cu_count * 3;
-        k = (int)((want + max_grid - 1) / max_grid);
-        if (k > 8) k = 8;
-    }
+    if (k == 0) k = 32;
     if (k < 1) k = 1;
     if (k > n_passes) k = n_passes;
     r->per_launch = k;

@@ -72,6 +72,79 @@ def test_ring_passes_match_the_oracle(env, oracle_lib, per_launch):
         svt.svt_ring_destroy(ring)
 
 
+def ring_case(svt, ctx, oracle_lib, batches, consts, n_passes, per_launch, runs=2):
+    """Fit the batches n_passes times round-robin in one ring; every batch's
+    results and the summary must equal the oracle's."""
+    import torch
+    svt.check(svt.svt_load_constants(ctx, consts.coef, consts.offset, consts.chi2_cut))
+    dbs = [svt.to_device(b) for b in batches]
+    drs = [svt.DeviceResults(b.n_events, b.n_roads) for b in batches]
+    wants, tot = [], dict(total_comb=0, total_pass=0, total_tracks=0)
+    for b in batches:
+        rc, w, _ = oracle_lib.fit_batch(b, consts, n_threads=8)
+        assert rc == 0
+        wants.append(w)
+    for p in range(n_passes):
+        summ = oracle_lib.fit_batch(batches[p % len(batches)], consts, n_threads=8)[2]
+        for k in tot:
+            tot[k] += summ[k]
+    st, ring = svt.svt_ring_create(ctx, [d.struct() for d in dbs], [r.struct() for r in drs],
+                                   n_passes, per_launch)
+    svt.check(st, "svt_ring_create")
+    try:
+        print(f"ring: {n_passes} passes, shape {svt.svt_ring_info(ring)}", flush=True)
+        for run in range(runs):
+            for r in drs:
+                for f in svt.RESULT_FIELDS:
+                    getattr(r, f).fill_(-3)
+            torch.cuda.synchronize()
+            st, t = svt.svt_ring_run(ring, torch.cuda.current_stream().cuda_stream)
+            svt.check(st, "svt_ring_run")
+            st, summ = svt.svt_result(ctx, t, -1)
+            svt.check(st, "ring result")
+            assert (summ.total_comb, summ.total_pass, summ.total_tracks) == \
+                (tot["total_comb"], tot["total_pass"], tot["total_tracks"])
+            assert summ.err_road == -1 and summ.err_event == -1
+            for i, (r, w) in enumerate(zip(drs, wants)):
+                assert_equal_results(r.numpy(), w, where=f"run {run}, batch {i}: ")
+    finally:
+        svt.svt_ring_destroy(ring)
+
+
+def shape_batches(seed=91):
+    """Batches whose chunks differ in kind: runs of events without roads, one
+    event of many sub-chunks, and events of ragged sizes."""
+    rng = np.random.default_rng(seed)
+    consts = synth.lattice_constants(rng)
+    out = []
+    rpe = np.zeros(600, np.int64)
+    rpe[rng.choice(600, 40, replace=False)] = rng.integers(1, 30, 40)
+    nr = int(rpe.sum())
+    out.append(synth.make_events(rng, rpe, rng.integers(0, 5, (nr, 4)), consts.n_sectors,
+                                 rng.random(nr) < 0.5, consts))
+    out.append(synth.make_events(rng, [3000], rng.integers(1, 6, (3000, 4)), consts.n_sectors,
+                                 rng.random(3000) < 0.5, consts))
+    rpe = rng.integers(1, 80, 400)
+    nr = int(rpe.sum())
+    out.append(synth.make_events(rng, rpe, rng.integers(1, 5, (nr, 4)), consts.n_sectors,
+                                 rng.random(nr) < 0.5, consts))
+    return out, consts
+
+
+@pytest.mark.parametrize("tuning", [dict(), dict(events_per_chunk=1), dict(events_per_chunk=3, schedule=2),
+                                    dict(blocks_per_cu=1), dict(events_per_chunk=256)])
+@pytest.mark.parametrize("per_launch", [3, 0])
+def test_ring_launch_shapes(env, oracle_lib, tuning, per_launch):
+    svt, ctx = env
+    batches, consts = shape_batches()
+    svt.check(svt.svt_set_tuning(ctx, **tuning))
+    try:
+        print(f"tuning {tuning}, {per_launch} per launch", flush=True)
+        ring_case(svt, ctx, oracle_lib, batches, consts, 8, per_launch)
+    finally:
+        svt.check(svt.svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=0, schedule=1, kernel=0))
+
+
 def test_ring_rules(env):
     svt, ctx = env
     b, c = synth.cfg1(n_events=20)
