@@ -57,8 +57,9 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the kernel source that is built now; else None."""
+    """HBM bytes per pass over the 3000-event batch from the committed counter
+    summary, if it was taken on the kernel source that is built now; else
+    None."""
     path = os.path.join(ROOT, "profiles", "fit_kernel_3000ev_hbm_counters.md")
     try:
         kv = {}
@@ -68,7 +69,7 @@ def measured_traffic():
                 kv[k.strip()] = v.strip()
         if kv.get("kernel_sha256_prefix") != kernel_source_hash():
             return None
-        return int(kv["traffic_bytes_per_launch"])
+        return int(kv["traffic_bytes_per_pass"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -219,6 +220,7 @@ def section_fit(args, svt, synth, torch):
     # a longer run of the same rings' shape for the steady-state check
     requests = section_fit_requests(args, svt, ctx, bs, rs, torch)
     alg = algorithmic_bytes(batch.n_events, batch.n_roads, batch.n_hits)
+    traffic = measured_traffic()
     # one launch covers passes / launches passes of alg bytes each
     achieved = alg * passes / launches / launch_s / 1e9
     out = dict(
@@ -235,7 +237,8 @@ def section_fit(args, svt, synth, torch):
                 "tuning": ctx.tuning(), "input_copies": args.copies, "ring_passes": per_ring,
                 "passes_per_launch": per_launch},
         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                  "frac": achieved / HBM_PEAK_GBS,
+                  "traffic": None if traffic is None else traffic * passes // launches,
                   "kernel_us": launch_s * 1e6, "kernel_us_per_pass": kernel_s * 1e6,
                   "algorithmic_bytes": alg * passes // launches, "algorithmic_bytes_per_pass": alg,
                   "passes_per_launch": per_launch, "timed_launches": launches,

@@ -1434,11 +1434,15 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads,
                                  batches[i].n_hits, false);
     // passes per launch: the block kernel takes several batches per launch
-    // (by default 32), which spreads the launch's start and its last blocks
-    // over many batches; the wavefront kernel takes one
+    // (by default up to 32, the passes split evenly over the launches), which
+    // spreads the launch's start and its last blocks over many batches; the
+    // wavefront kernel takes one
     int k = passes_per_launch;
     if (c->tuning.kernel == 2) k = 1;
-    if (k == 0) k = 32;
+    if (k == 0) {
+        const int launches = (n_passes + 31) / 32;
+        k = (n_passes + launches - 1) / launches;
+    }
     if (k < 1) k = 1;
     if (k > n_passes) k = n_passes;
     r->per_launch = k;
