@@ -50,13 +50,13 @@ def test_traffic_follows_the_profiled_source(tmp_path, monkeypatch):
     (prof / "fit_kernel_3000ev_hbm_counters.md").write_text(
         "| x | 1 |\n"
         f"kernel_sha256_prefix = {bench.kernel_source_hash()}\n"
-        "traffic_bytes_per_launch = 12345\n")
+        "traffic_bytes_per_pass = 12345\n")
     src = os.path.join(bench.ROOT, "paper_1311_0380_amd")
     (tmp_path / "paper_1311_0380_amd").symlink_to(src)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic() == 12345
     (prof / "fit_kernel_3000ev_hbm_counters.md").write_text(
-        "kernel_sha256_prefix = 0000000000000000\ntraffic_bytes_per_launch = 12345\n")
+        "kernel_sha256_prefix = 0000000000000000\ntraffic_bytes_per_pass = 12345\n")
     assert bench.measured_traffic() is None
     (prof / "fit_kernel_3000ev_hbm_counters.md").unlink()
     assert bench.measured_traffic() is None
