@@ -122,21 +122,20 @@ typedef struct {
                                svt_set_timing left untimed                          */
 } svt_summary;
 
-/* Launch shape of the fit.  Kernel 1 (the default) gives each block a chunk
- * of events and aims for 256 roads per chunk; kernel 2 gives each wavefront
- * its own chunk (at most 63 events; it aims for 64 roads).  Results are the
- * same bit for bit either way. */
+/* Launch shape of the fit: each block takes a chunk of events (by default
+ * sized for about 256 roads).  Results are the same bit for bit whatever the
+ * shape. */
 typedef struct {
     int32_t events_per_chunk;  /* events per work item (1..256); 0 = automatic    */
     int32_t blocks_per_cu;     /* grid = CUs * blocks_per_cu (1..16), fewer when
                                   there are fewer chunks; 0 = automatic           */
     int32_t schedule;          /* 1 = cyclic (item w -> worker w mod workers),
-                                  2 = blocked, 3 = balanced by roads (kernel 1:
-                                  each block takes the events whose first road
-                                  falls in its equal share of the roads; kernel
-                                  2 treats 3 as 1); 0 keeps the current value    */
-    int32_t kernel;            /* 0 = automatic (1), 1 = block per chunk,
-                                  2 = wavefront per chunk                         */
+                                  2 = blocked, 3 = balanced by roads (each block
+                                  takes the events whose first road falls in its
+                                  equal share of the roads); 0 keeps the current
+                                  value                                           */
+    int32_t kernel;            /* 0 or 1: the block-per-chunk kernel (the only
+                                  one; other values are SVT_E_INVAL)              */
 } svt_tuning;
 
 /*
@@ -365,10 +364,10 @@ svt_status svt_plan_fit(svt_plan *plan, const svt_event_batch *batch, const svt_
  * (svt_ring_run returns SVT_E_STATE).  Destroy rings before their context.
  * ------------------------------------------------------------------------ */
 typedef struct svt_ring svt_ring;
-/* passes_per_launch: passes one kernel launch of the block kernel covers
- * (each of its batches spread over the same number of blocks), 1..64, or 0
- * for automatic (at most 32, the passes split evenly over the launches); the
- * wavefront kernel takes one pass per launch.  Results do not depend on it. */
+/* passes_per_launch: passes one kernel launch covers (each of its batches
+ * spread over the same number of blocks), 1..64, or 0 for automatic (at most
+ * 32, the passes split evenly over the launches).  Results do not depend on
+ * it. */
 svt_status svt_ring_create(svt_ctx *ctx, int32_t n_batches, const svt_event_batch *batches,
                            const svt_results *results, int32_t n_passes, int32_t passes_per_launch,
                            svt_ring **out);

@@ -182,7 +182,7 @@ __device__ __forceinline__ void run_rows(Row &st, const int16_t *hit, uint32_t p
             const uint32_t sel = ((n2m - 1) << 2) | (n3m - 1);
 #define SVT_SMALL(N2, N3)                                                         \
     case ((N2 - 1) << 2) | (N3 - 1):                                              \
-        if (uni) frac_small<N2, N3, true>(st, hit, p2, p3, rn2, rn3, lim);        \
+        if (uni) frac_small<N2, N3>(st, hit, p2, p3, rn2, lim);                   \
         else frac_small_masked<N2, N3>(st, hit, p2, p3, rn2, rn3, lim);           \
         return;
             switch (sel) {

@@ -26,20 +26,6 @@ constexpr int kCstIntB = 36;      // int32 index of the constraint offsets
 constexpr int kCstIntP = 40;      // int32 index of the parameter columns
 constexpr int kCstIntPB = 58;     // int32 index of the parameter offsets
 
-// Sector tables of the wave kernel, built by svt_load_constants:
-//   pb   [n_sectors][14] fp64  columns 0..3 of constraint rows 3..5, [col * 3 + row],
-//                              2 pad (112-byte stride: sectors of a wavefront's
-//                              16-byte LDS reads spread over all 8 bank groups)
-//   base [n_sectors][12] fp64  A[3..5][4], A[3..5][5], b[3..5], 3 zeros
-//   par  [n_sectors][24] int32 row k of 0..2 at [k * 8]: A[k][0..5], b[k], 0
-constexpr int kCstPbStride = 14;
-constexpr int kCstBaseStride = 12;
-constexpr int kCstParStride = 24;
-constexpr int kCstWaveBytes = (kCstPbStride + kCstBaseStride) * 8 + kCstParStride * 4;
-constexpr int kWaveMaxEvents = 63;        // events per chunk of the wave kernel
-constexpr int kWaveTargetRoads = 64;      // roads per chunk it aims for
-constexpr int kWaveBlocksPerCu = 3;       // default: 3 waves per SIMD (VGPR-limited)
-
 // Sizes of a batch when they are read from device memory (graph replay).
 struct Sizes {
     int32_t n_events, n_roads, n_hits;
@@ -83,10 +69,7 @@ struct FitArgs {
     int32_t *params;
     uint32_t *hit_index4;       // 4 x uint8 per road
     int32_t *ntracks;
-    const double *cst_block;    // block-kernel LDS image: [n_sectors][kCstStride]
-    const double *cst_pb;       // wave-kernel sector tables (device)
-    const double *cst_base;
-    const int32_t *cst_par;
+    const double *cst_block;    // the kernel's LDS image of the constants: [n_sectors][kCstStride]
     int32_t frac_key;           // 1: cut < 2^44, minimise chi2 + index / 256
     // launch shape
     int32_t events_per_chunk;
@@ -118,9 +101,6 @@ hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t st
 // holding one FitArgs per batch; batch i is spread over blocks [i per, (i+1) per).
 hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, size_t dyn_lds,
                             hipStream_t stream);
-hipError_t prepare_fit_wave();
-hipError_t launch_fit_wave(const FitArgs &a, int grid, hipStream_t stream,
-                           hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // One thread copies a request's sequence number from host-mapped memory to
 // device memory (the first node of a ring's graph; the fit kernels then read
 // it from device memory).

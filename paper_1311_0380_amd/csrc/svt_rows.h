@@ -1,7 +1,7 @@
-// Row loops of the SVT fit shared by the fit kernels (arXiv:1311.0380,
-// Sec. 2).  A road's combinations are split into rows: two of its layers
-// index the rows, the other two (the inner layers, a before b in layer
-// order) are looped over inside each row.  For one row these loops give
+// Row loops of the SVT fit kernel (arXiv:1311.0380, Sec. 2).  A road's
+// combinations are split into rows: two of its layers index the rows, the
+// other two (the inner layers, a before b in layer order) are looped over
+// inside each row.  For one row these loops give
 // every combination's constraint rows y3..y5 and chi2 in fp64, the pass
 // count and the best.  Below, p2/n2 are the staged hit list and hit count
 // of inner layer a, p3/n3 those of inner layer b.
@@ -23,14 +23,6 @@
 
 namespace svt {
 namespace {
-
-// Orders the wave's earlier LDS writes before its later LDS reads.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // DPP controls: row_shr:n shifts within a row of 16 lanes; row_bcast:15 and
 // row_bcast:31 carry lane 15 / lane 31 into the following rows.
@@ -76,23 +68,6 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t x)
     x = min(x, dpp_or_max<kRowBcast15, 0xA>(x));
     x = min(x, dpp_or_max<kRowBcast31, 0xC>(x));
     return __builtin_amdgcn_readlane(x, 63);
-}
-
-// Maximum across the wavefront (all lanes active), as a uniform value.
-__device__ __forceinline__ uint32_t wave_max(uint32_t x)
-{
-    x = max(x, dpp<kRowShr + 1, 0xF, true>(x));
-    x = max(x, dpp<kRowShr + 2, 0xF, true>(x));
-    x = max(x, dpp<kRowShr + 4, 0xF, true>(x));
-    x = max(x, dpp<kRowShr + 8, 0xF, true>(x));
-    x = max(x, dpp<kRowBcast15, 0xA, false>(x));
-    x = max(x, dpp<kRowBcast31, 0xC, false>(x));
-    return __builtin_amdgcn_readlane(x, 63);
-}
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
@@ -158,21 +133,18 @@ __device__ __forceinline__ bool row_key(const Row &st, double cut, uint32_t rowb
 }
 
 // Small rows, fully unrolled: N2 = the wavefront's largest n2, N3 = its n3
-// (uniform) or largest n3 (UNI false).  All hits are loaded up front.  i2 past
-// the lane's n2 is masked off, so its word is read unclamped (the staged hit
-// array carries a pad of 16 words for this); i3 past the lane's n3 (mixed
-// wavefronts only) is clamped into the list, computes a duplicate with a
-// larger fraction that never wins and is kept out of the pass count.
-template <int N2, int N3, bool UNI>
+// (the same in every lane).  All hits are loaded up front.  i2 past the
+// lane's n2 is masked off, so its word is read unclamped (the staged hit
+// array carries a pad of 16 words for this).
+template <int N2, int N3>
 __device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
-                                           uint32_t n2, uint32_t n3, double lim)
+                                           uint32_t n2, double lim)
 {
-    const uint32_t l3 = n3 - 1;
     double h2[N2], h3[N3];
 #pragma unroll
     for (int i = 0; i < N2; ++i) h2[i] = (double)hit[p2 + i];
 #pragma unroll
-    for (int i = 0; i < N3; ++i) h3[i] = (double)hit[p3 + (UNI ? (uint32_t)i : min((uint32_t)i, l3))];
+    for (int i = 0; i < N3; ++i) h3[i] = (double)hit[p3 + i];
 #pragma unroll
     for (int i2 = 0; i2 < N2; ++i2) {
         if (i2 == 0 || (uint32_t)i2 < n2) {
@@ -186,12 +158,7 @@ __device__ __forceinline__ void frac_small(Row &st, const int16_t *hit, uint32_t
                 const double y5 = fma(st.c5, h3[i3], q5);
                 const double v =
                     fma(y5, y5, fma(y4, y4, fma(y3, y3, (i2 * 16 + i3) * (1.0 / 256))));
-                if constexpr (UNI) {
-                    count_le(st.np, v, lim);
-                } else {
-                    const bool pass = v <= lim && (uint32_t)i3 < n3;
-                    st.np += pass ? 1u : 0u;
-                }
+                count_le(st.np, v, lim);
                 st.best = dmin(st.best, v);
             }
         }
@@ -330,55 +297,6 @@ __device__ __forceinline__ void gen_mixed(Row &st, const int16_t *hit, uint32_t 
             st.best = better ? c : st.best;
             st.bidx = better ? ((i2 << 4) | i3) : st.bidx;
         }
-    }
-}
-
-template <bool F>
-__device__ __forceinline__ void run_row(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
-                                        uint32_t rn2, uint32_t rn3, double lim)
-{
-    // rows are sorted by (n3, n2): the last lane holds the wavefront's largest
-    const uint32_t n3f = __builtin_amdgcn_readfirstlane(rn3);
-    const uint32_t n3l = __builtin_amdgcn_readlane(rn3, 63);
-    const uint32_t n2w = __builtin_amdgcn_readlane(rn2, 63);
-    if constexpr (F) {
-        // both inner trip counts at most 4: the unrolled forms
-        const uint32_t n3w = n3f == n3l ? n3l : wave_max(rn3);
-        const uint32_t n2m = n3f == n3l ? n2w : wave_max(rn2);
-        if (n2m <= 4 && n3w <= 4) {
-            const uint32_t sel = ((n2m - 1) << 2) | (n3w - 1);
-#define SVT_SMALL(N2, N3)                                                             \
-    case ((N2 - 1) << 2) | (N3 - 1):                                                  \
-        if (n3f == n3l) frac_small<N2, N3, true>(st, hit, p2, p3, rn2, rn3, lim);     \
-        else frac_small<N2, N3, false>(st, hit, p2, p3, rn2, rn3, lim);               \
-        return;
-            switch (sel) {
-                SVT_SMALL(1, 1) SVT_SMALL(1, 2) SVT_SMALL(1, 3) SVT_SMALL(1, 4)
-                SVT_SMALL(2, 1) SVT_SMALL(2, 2) SVT_SMALL(2, 3) SVT_SMALL(2, 4)
-                SVT_SMALL(3, 1) SVT_SMALL(3, 2) SVT_SMALL(3, 3) SVT_SMALL(3, 4)
-                SVT_SMALL(4, 1) SVT_SMALL(4, 2) SVT_SMALL(4, 3) SVT_SMALL(4, 4)
-            default: break;
-            }
-#undef SVT_SMALL
-        }
-    }
-    if (n3f == n3l) {
-#define SVT_CASE(N)                                                          \
-    case N:                                                                  \
-        if constexpr (F) frac_uniform<N>(st, hit, p2, p3, rn2, n2w, lim);    \
-        else gen_uniform<N>(st, hit, p2, p3, rn2, n2w, lim);                 \
-        break;
-        switch (n3f) {
-            SVT_CASE(1) SVT_CASE(2) SVT_CASE(3) SVT_CASE(4) SVT_CASE(5) SVT_CASE(6)
-            SVT_CASE(7) SVT_CASE(8) SVT_CASE(9) SVT_CASE(10) SVT_CASE(11) SVT_CASE(12)
-            SVT_CASE(13) SVT_CASE(14) SVT_CASE(15) SVT_CASE(16)
-        default: break;
-        }
-#undef SVT_CASE
-    } else {
-        const uint32_t n2m = wave_max(rn2);
-        if constexpr (F) frac_mixed(st, hit, p2, p3, rn2, rn3, n2m, n3l, lim);
-        else gen_mixed(st, hit, p2, p3, rn2, rn3, n2m, n3l, lim);
     }
 }
 

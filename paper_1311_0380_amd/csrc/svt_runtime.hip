@@ -108,7 +108,6 @@ struct svt_ctx {
     // constants
     int32_t *coef = nullptr;
     int32_t *offset = nullptr;
-    void *cst_wave = nullptr;                // sector tables of the wave kernel
     void *cst_block = nullptr;               // LDS image of the block kernel's table
     int32_t n_sectors = 0;
     uint64_t cut = 0;
@@ -298,12 +297,10 @@ int block_roads_per_chunk(int32_t n_roads, int32_t n_hits, int64_t slots)
     return roads;
 }
 
-// Kernel, chunking and grid of a launch.  The wave kernel takes a chunk per
-// wavefront (4 per block), the block kernel a chunk per block.  A persistent
-// grid (graph plans) keeps the full size; otherwise the grid shrinks to the
-// number of chunks.
+// Chunking and grid of a launch of the fit kernel (a chunk per block).  A
+// persistent grid (graph plans) keeps the full size; otherwise the grid
+// shrinks to the number of chunks.
 struct LaunchShape {
-    int kernel;   // 1 block per chunk, 2 wavefront per chunk
     int epc;      // events per chunk
     int grid;
 };
@@ -312,34 +309,20 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
                          bool persistent)
 {
     LaunchShape ls;
-    ls.kernel = t.kernel == 2 ? 2 : 1;
-    int bpc;
-    int64_t per_block;
-    if (ls.kernel == 2) {
-        ls.epc = t.events_per_chunk > 0
-                     ? (t.events_per_chunk < svt::kWaveMaxEvents ? t.events_per_chunk
-                                                                 : svt::kWaveMaxEvents)
-                     : auto_events_per_chunk(ne, nr, svt::kWaveTargetRoads, svt::kWaveMaxEvents);
-        bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : svt::kWaveBlocksPerCu;
-        per_block = svt::kBlock / 64;
-    } else {
-        bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 3;
-        ls.epc = t.events_per_chunk > 0
-                     ? t.events_per_chunk
-                     : auto_events_per_chunk(ne, nr,
-                                             block_roads_per_chunk(nr, nh, (int64_t)c->cu_count * bpc),
-                                             svt::kMaxEventsPerChunk);
-        per_block = 1;
-    }
+    const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 3;
+    ls.epc = t.events_per_chunk > 0
+                 ? t.events_per_chunk
+                 : auto_events_per_chunk(ne, nr,
+                                         block_roads_per_chunk(nr, nh, (int64_t)c->cu_count * bpc),
+                                         svt::kMaxEventsPerChunk);
     int64_t grid = (int64_t)c->cu_count * bpc;
-    if (!persistent && ls.kernel == 1 && t.schedule == 3) {
+    if (!persistent && t.schedule == 3) {
         // balanced by roads: at least 64 roads per block
         const int64_t need = ((int64_t)nr + 63) / 64;
         if (grid > need) grid = need;
     } else if (!persistent) {
         const int64_t n_chunks = ne > 0 ? ((int64_t)ne + ls.epc - 1) / ls.epc : 0;
-        const int64_t need = (n_chunks + per_block - 1) / per_block;
-        if (grid > need) grid = need;
+        if (grid > n_chunks) grid = n_chunks;
     }
     if (grid < 1) grid = 1;
     ls.grid = (int)grid;
@@ -349,11 +332,6 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
 // The launch arguments that follow from the context's tables and the shape.
 void set_shape_args(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &ls)
 {
-    const char *w = static_cast<const char *>(c->cst_wave);
-    a.cst_pb = reinterpret_cast<const double *>(w);
-    a.cst_base = reinterpret_cast<const double *>(w + (size_t)256 * svt::kCstPbStride * 8);
-    a.cst_par = reinterpret_cast<const int32_t *>(
-        w + (size_t)256 * (svt::kCstPbStride + svt::kCstBaseStride) * 8);
     a.frac_key = c->cut < (1ull << 44) ? 1 : 0;
     a.cst_block = static_cast<const double *>(c->cst_block);
     a.events_per_chunk = ls.epc;
@@ -363,7 +341,6 @@ hipError_t launch_shaped(const svt_ctx *c, svt::FitArgs &a, const LaunchShape &l
                          hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr)
 {
     set_shape_args(c, a, ls);
-    if (ls.kernel == 2) return svt::launch_fit_wave(a, ls.grid, st, start, stop);
     return svt::launch_fit(a, ls.grid, (size_t)c->n_sectors * svt::kCstBytesPerSector, st, start,
                            stop);
 }
@@ -436,7 +413,6 @@ svt_status svt_create(svt_ctx **out, int32_t device, size_t hbm_budget_bytes)
     snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
     c->max_grid = c->cu_count * svt::kMaxBlocksPerCu;
     e = svt::prepare_fit();
-    if (e == hipSuccess) e = svt::prepare_fit_wave();
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "fit kernel attributes");
@@ -490,7 +466,6 @@ svt_status svt_destroy(svt_ctx *c)
         if (s.scan.ptr) (void)hipFree(s.scan.ptr);
     }
     if (c->coef) (void)hipFree(c->coef);
-    if (c->cst_wave) (void)hipFree(c->cst_wave);
     if (c->cst_block) (void)hipFree(c->cst_block);
     if (c->shadow_scratch.ptr) (void)hipFree(c->shadow_scratch.ptr);
     for (DevBuf &b : c->pool) (void)hipFree(b.ptr);
@@ -521,10 +496,6 @@ svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef
         c->coef = static_cast<int32_t *>(p);
         c->offset = c->coef + 256 * 36;
     }
-    if (c->cst_wave == nullptr) {
-        svt_status st = dev_alloc(c, &c->cst_wave, (size_t)256 * svt::kCstWaveBytes);
-        if (st != SVT_OK) return st;
-    }
     if (c->cst_block == nullptr) {
         svt_status st = dev_alloc(c, &c->cst_block, (size_t)256 * svt::kCstBytesPerSector);
         if (st != SVT_OK) return st;
@@ -532,24 +503,6 @@ svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef
     HIP_TRY(hipMemcpy(c->coef, coef, sizeof(int32_t) * 36 * n_sectors, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->offset, offset, sizeof(int32_t) * 6 * n_sectors, hipMemcpyHostToDevice));
     {
-        // wave-kernel tables (see svt_internal.h for the layout)
-        std::vector<double> pb((size_t)256 * svt::kCstPbStride, 0.0);
-        std::vector<double> bs((size_t)256 * svt::kCstBaseStride, 0.0);
-        std::vector<int32_t> par((size_t)256 * svt::kCstParStride, 0);
-        for (int s = 0; s < n_sectors; ++s) {
-            const int32_t *A = coef + s * 36, *b = offset + s * 6;
-            for (int col = 0; col < 4; ++col)
-                for (int k = 0; k < 3; ++k)
-                    pb[(size_t)s * svt::kCstPbStride + col * 3 + k] = (double)A[(3 + k) * 6 + col];
-            for (int k = 0; k < 3; ++k) {
-                bs[(size_t)s * svt::kCstBaseStride + k] = (double)A[(3 + k) * 6 + 4];
-                bs[(size_t)s * svt::kCstBaseStride + 3 + k] = (double)A[(3 + k) * 6 + 5];
-                bs[(size_t)s * svt::kCstBaseStride + 6 + k] = (double)b[3 + k];
-                for (int col = 0; col < 6; ++col)
-                    par[(size_t)s * svt::kCstParStride + k * 8 + col] = A[k * 6 + col];
-                par[(size_t)s * svt::kCstParStride + k * 8 + 6] = b[k];
-            }
-        }
         // the block kernel's LDS image (see svt_internal.h for the layout)
         std::vector<double> img((size_t)n_sectors * svt::kCstStride, 0.0);
         for (int s = 0; s < n_sectors; ++s) {
@@ -567,11 +520,6 @@ svt_status svt_load_constants(svt_ctx *c, int32_t n_sectors, const int32_t *coef
             }
         }
         HIP_TRY(hipMemcpy(c->cst_block, img.data(), img.size() * 8, hipMemcpyHostToDevice));
-        char *w = static_cast<char *>(c->cst_wave);
-        HIP_TRY(hipMemcpy(w, pb.data(), pb.size() * 8, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(w + pb.size() * 8, bs.data(), bs.size() * 8, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(w + (pb.size() + bs.size()) * 8, par.data(), par.size() * 4,
-                          hipMemcpyHostToDevice));
     }
     c->n_sectors = n_sectors;
     c->cut = chi2_cut;
@@ -586,7 +534,7 @@ svt_status svt_set_tuning(svt_ctx *c, const svt_tuning *t)
     if (t->events_per_chunk < 0 || t->events_per_chunk > svt::kMaxEventsPerChunk) return SVT_E_INVAL;
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > svt::kMaxBlocksPerCu) return SVT_E_INVAL;
     if (t->schedule < 0 || t->schedule > 3) return SVT_E_INVAL;
-    if (t->kernel < 0 || t->kernel > 2) return SVT_E_INVAL;
+    if (t->kernel < 0 || t->kernel > 1) return SVT_E_INVAL;
     c->tuning.events_per_chunk = t->events_per_chunk;   // 0 = automatic
     c->tuning.blocks_per_cu = t->blocks_per_cu;         // 0 = automatic
     if (t->schedule) c->tuning.schedule = t->schedule;
@@ -1183,7 +1131,7 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
         if (tuning->events_per_chunk < 0 || tuning->events_per_chunk > svt::kMaxEventsPerChunk ||
             tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > svt::kMaxBlocksPerCu ||
             tuning->schedule < 0 || tuning->schedule > 3 || tuning->kernel < 0 ||
-            tuning->kernel > 2) {
+            tuning->kernel > 1) {
             delete p;
             return SVT_E_INVAL;
         }
@@ -1433,12 +1381,10 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     for (int i = 0; i < n_batches; ++i)
         shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads,
                                  batches[i].n_hits, false);
-    // passes per launch: the block kernel takes several batches per launch
-    // (by default up to 32, the passes split evenly over the launches), which
-    // spreads the launch's start and its last blocks over many batches; the
-    // wavefront kernel takes one
+    // passes per launch: several batches per launch (by default up to 32,
+    // the passes split evenly over the launches) spread the launch's start
+    // and its last blocks over many batches
     int k = passes_per_launch;
-    if (c->tuning.kernel == 2) k = 1;
     if (k == 0) {
         const int launches = (n_passes + 31) / 32;
         k = (n_passes + launches - 1) / launches;

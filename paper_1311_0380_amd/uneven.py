@@ -20,7 +20,7 @@ CACHE_PATH = os.environ.get(
                  "svt_tune.json"))
 
 
-CACHE_VERSION = "shapes4"     # bump when the candidate set or the kernels change
+CACHE_VERSION = "shapes5"     # bump when the candidate set or the kernels change
 
 
 def workload_signature(n_events, n_roads, n_hits, ncomb_total=None):
@@ -33,25 +33,18 @@ def workload_signature(n_events, n_roads, n_hits, ncomb_total=None):
 
 
 def candidates(n_events, n_roads):
-    """Launch shapes to try: the block-per-chunk kernel around 128..512 roads
-    per chunk, or with each block's events found by road count (schedule 3),
-    and the wavefront-per-chunk kernel around 16..128, each with a few
-    occupancies."""
+    """Launch shapes to try: chunks of about 128..512 roads, cyclic or
+    blocked, or each block's events found by road count (schedule 3), each
+    with a few occupancies."""
     rpe = max(1.0, n_roads / max(1, n_events))
     out = []
-    for e in (1, 2, 4, 8, 16, 32, 63):
-        if 16 <= e * rpe <= 128 or (e == 1 and rpe > 128):
-            for bpc in (3, 4):
-                for sch in (1, 2):
-                    out.append(dict(events_per_chunk=e, blocks_per_cu=bpc, schedule=sch, kernel=2))
     for e in (1, 2, 4, 8, 16, 32, 64, 128, 256):
         if 128 <= e * rpe <= 512 or (e == 1 and rpe > 512):
             for bpc in (2, 3):
-                out.append(dict(events_per_chunk=e, blocks_per_cu=bpc, schedule=1, kernel=1))
+                for sch in (1, 2):
+                    out.append(dict(events_per_chunk=e, blocks_per_cu=bpc, schedule=sch, kernel=1))
     for bpc in (2, 3):
         out.append(dict(events_per_chunk=256, blocks_per_cu=bpc, schedule=3, kernel=1))
-    if not out:
-        out = [dict(events_per_chunk=0, blocks_per_cu=0, schedule=1, kernel=k) for k in (1, 2)]
     return out
 
 

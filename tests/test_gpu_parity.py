@@ -150,13 +150,15 @@ def restore_tuning(ctx):
     svt.check(svt.svt_set_tuning(ctx, events_per_chunk=0, blocks_per_cu=0, schedule=1, kernel=0))
 
 
+def test_only_the_block_kernel(ctx):
+    from paper_1311_0380_amd import svt
+    assert svt.svt_set_tuning(ctx, kernel=2) == svt.SVT_E_INVAL
+    assert svt.svt_set_tuning(ctx, kernel=-1) == svt.SVT_E_INVAL
+    svt.check(svt.svt_set_tuning(ctx, kernel=1))
+    restore_tuning(ctx)
+
+
 @pytest.mark.parametrize("tuning", [
-    # wavefront per chunk; 256 events per chunk clamps to 63
-    dict(kernel=2), dict(kernel=2, events_per_chunk=1), dict(kernel=2, events_per_chunk=7),
-    dict(kernel=2, events_per_chunk=63), dict(kernel=2, events_per_chunk=256),
-    dict(kernel=2, blocks_per_cu=1, schedule=1), dict(kernel=2, blocks_per_cu=4, schedule=1),
-    dict(kernel=2, blocks_per_cu=8, schedule=2), dict(kernel=2, events_per_chunk=3, schedule=2),
-    # block per chunk (the default)
     dict(kernel=1), dict(kernel=1, events_per_chunk=1), dict(kernel=1, events_per_chunk=7),
     dict(kernel=1, events_per_chunk=256), dict(kernel=1, blocks_per_cu=1, schedule=1),
     dict(kernel=1, blocks_per_cu=3, schedule=1), dict(kernel=1, blocks_per_cu=8, schedule=2),
@@ -164,7 +166,7 @@ def restore_tuning(ctx):
     # balanced by roads: each block's event range split into chunks of E
     dict(kernel=1, schedule=3), dict(kernel=1, schedule=3, events_per_chunk=1),
     dict(kernel=1, schedule=3, events_per_chunk=5, blocks_per_cu=1),
-    dict(kernel=1, schedule=3, blocks_per_cu=16), dict(kernel=2, schedule=3)])
+    dict(kernel=1, schedule=3, blocks_per_cu=16)])
 def test_launch_shapes_same_bits(ctx, oracle_lib, tuning):
     from paper_1311_0380_amd import svt
     batch, consts = synth.cfg3(n_events=2000)
@@ -175,21 +177,21 @@ def test_launch_shapes_same_bits(ctx, oracle_lib, tuning):
         restore_tuning(ctx)
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("schedule", [1, 3])
 @pytest.mark.parametrize("cut", [1 << 32, (1 << 44) - 1, 1 << 44, (1 << 48) - 1])
-def test_cut_forms_and_deep_layers(ctx, oracle_lib, kernel, cut):
+def test_cut_forms_and_deep_layers(ctx, oracle_lib, schedule, cut):
     """Up to 16 hits per layer (every inner trip count 1..16, rows of up to
     256 combinations per (i0, i1)), cuts on both sides of 2^44 (where the
     kernel switches between the fraction-encoded minimum and the general
     compare-and-select form) and at the largest allowed value."""
     from paper_1311_0380_amd import svt
-    rng = np.random.default_rng(44 + kernel)
+    rng = np.random.default_rng(44 + schedule)
     consts = synth.lattice_constants(rng, chi2_cut=cut)
     batch = synth.random_small(rng, n_events=40, max_roads=10, max_hits=16, n_sectors=72,
                                consts=consts, track_frac=0.5)
     try:
-        svt.check(svt.svt_set_tuning(ctx, kernel=kernel, schedule=1))
-        got, summ = check_case(ctx, oracle_lib, batch, consts, f"kernel {kernel} cut {cut}: ")
+        svt.check(svt.svt_set_tuning(ctx, schedule=schedule))
+        got, summ = check_case(ctx, oracle_lib, batch, consts, f"schedule {schedule} cut {cut}: ")
         assert summ["total_pass"] > 0
     finally:
         restore_tuning(ctx)

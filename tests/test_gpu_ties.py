@@ -6,10 +6,11 @@ batches here repeat hit words inside a layer on purpose: in roads with a
 planted track the true word is copied to other places of its layer (several
 combinations then reach chi2 = 0), and in every road some words are copied
 onto others (every combination through them has a twin).  Twins share every
-fit input, so they tie exactly whatever the constants.  Both fit kernels run
-at a cut below 2^44 (the fraction-encoded minimum) and above it (the general
+fit input, so they tie exactly whatever the constants.  The fit runs at a
+cut below 2^44 (the fraction-encoded minimum) and above it (the general
 compare-and-select), with inner-layer counts up to 4, 8 and 16 and mixed
-counts in a wavefront; every field is compared with the oracle."""
+counts in a wavefront, with the default chunks and with one event per
+chunk; every field is compared with the oracle."""
 import pytest
 
 from tests.gpu_helpers import assert_equal_results, lib_fit
@@ -26,10 +27,10 @@ def ctx():
     svt.svt_destroy(h)
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("events_per_chunk", [0, 1])
 @pytest.mark.parametrize("cut", [1 << 32, (1 << 44) + 12345])
 @pytest.mark.parametrize("max_hits", [4, 8, 16])
-def test_lowest_index_wins_ties(ctx, oracle_lib, kernel, cut, max_hits):
+def test_lowest_index_wins_ties(ctx, oracle_lib, events_per_chunk, cut, max_hits):
     from paper_1311_0380_amd import svt
     batch, consts = tie_batch(900 + max_hits, max_hits)
     consts.chi2_cut = cut
@@ -41,11 +42,12 @@ def test_lowest_index_wins_ties(ctx, oracle_lib, kernel, cut, max_hits):
     assert n_twin >= batch.n_roads // 10, n_twin
     assert viol == 0
     svt.check(svt.svt_load_constants(ctx, consts.coef, consts.offset, consts.chi2_cut))
-    svt.check(svt.svt_set_tuning(ctx, kernel=kernel))
+    svt.check(svt.svt_set_tuning(ctx, events_per_chunk=events_per_chunk))
     try:
         st, summ, got = lib_fit(ctx, batch)
     finally:
-        svt.check(svt.svt_set_tuning(ctx, kernel=0))
+        svt.check(svt.svt_set_tuning(ctx, events_per_chunk=0))
     assert st == 0, (st, summ)
-    assert_equal_results(got, want, where=f"kernel {kernel} cut {cut} max_hits {max_hits}: ")
+    assert_equal_results(got, want,
+                         where=f"events per chunk {events_per_chunk} cut {cut} max_hits {max_hits}: ")
     assert summ["total_pass"] == wsum["total_pass"]
