@@ -675,7 +675,8 @@ __device__ __forceinline__ void chunk_range(int32_t n_chunks, int32_t schedule, 
 // (the host reduces them); the wavefront sums are uniform already.  Lane and
 // wave ids are recomputed here rather than kept live across the whole kernel.
 // Every thread calls it (one barrier).
-__device__ __forceinline__ void write_partial(const FitArgs &a, int32_t blk, const Acc &acc)
+__device__ __forceinline__ void write_partial(const FitArgs &a, int32_t blk, const Acc &acc,
+                                              uint32_t seq)
 {
     const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
@@ -692,16 +693,9 @@ __device__ __forceinline__ void write_partial(const FitArgs &a, int32_t blk, con
             p.err_road = min(p.err_road, s_part[w].err_road);
             p.err_event = min(p.err_event, s_part[w].err_event);
         }
-        p.seq = request_seq(a);
+        p.seq = seq;
         a.partials[blk] = p;
     }
-}
-
-// The partial of a batch the block has no chunk of.
-__device__ __forceinline__ void write_zero_partial(const FitArgs &a, int32_t blk)
-{
-    if (threadIdx.x == 0)
-        a.partials[blk] = BlockPartial{0, 0, 0, 0xFFFFFFFFu, 0xFFFFFFFFu, request_seq(a)};
 }
 
 // One block's share of one batch: block blk of the nblk blocks the batch is
@@ -715,11 +709,20 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     __shared__ __align__(16) Shared S;
     const int tid = threadIdx.x;
 
+    // sizes and sequence number: from the launch arguments, or read once per
+    // block from the plan's host-mapped descriptor (all four words in one
+    // load: reads of one host word by every block queue behind each other)
+    // or the ring's device word
     int32_t n_events = a.n_events, n_roads = a.n_roads, n_hits = a.n_hits;
+    uint32_t seq = a.seq;
     if (a.sizes != nullptr) {
-        n_events = a.sizes->n_events;
-        n_roads = a.sizes->n_roads;
-        n_hits = a.sizes->n_hits;
+        const uint4 sz = *reinterpret_cast<const uint4 *>(a.sizes);
+        n_events = (int32_t)sz.x;
+        n_roads = (int32_t)sz.y;
+        n_hits = (int32_t)sz.z;
+        seq = sz.w;
+    } else if (a.seq_dev != nullptr) {
+        seq = *a.seq_dev;
     }
     const int32_t n_sectors = a.n_sectors;
     double *s_cd = reinterpret_cast<double *>(s_dyn);
@@ -826,7 +829,7 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     }
     staged = !copy_image;
 
-    write_partial(a, blk, acc);
+    write_partial(a, blk, acc, seq);
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))

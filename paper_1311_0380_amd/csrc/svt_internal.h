@@ -79,19 +79,6 @@ struct FitArgs {
     uint32_t seq;
 };
 
-// The sequence number a fit kernel writes into its partial sums: from the
-// ring's device word, the plan's host-mapped sizes or the launch arguments.
-// (Relaxed atomic loads: plain ones were merged into one load through a
-// pointer that could also point at a stack copy of a.seq.)
-__device__ __forceinline__ uint32_t request_seq(const FitArgs &a)
-{
-    if (a.seq_dev != nullptr)
-        return __hip_atomic_load(a.seq_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (a.sizes != nullptr)
-        return __hip_atomic_load(&a.sizes->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    return a.seq;
-}
-
 hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
 // start/stop non-NULL: the dispatch itself records them around the kernel
 // (no separate event packets on the stream).
