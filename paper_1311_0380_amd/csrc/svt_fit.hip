@@ -292,10 +292,23 @@ __device__ __forceinline__ void window_loads_hits(const FitArgs &a, int32_t hw, 
         // chunk loop would stay live across the row loops
         asm volatile("" : "+v"(t));
         in.hv[q] = make_uint4(0u, 0u, 0u, 0u);
-        if (vec && t + 8 <= W) {
-            in.hv[q] = *reinterpret_cast<const uint4 *>(a.hits + hw + t);
+        if (vec && t < W && hw + t + 8 <= n_hits) {
+            // a whole 16-byte group of the array; in the window's last group
+            // the words past the window are zeroed
+            uint4 v = *reinterpret_cast<const uint4 *>(a.hits + hw + t);
+            if (t + 8 > W) {
+                const int32_t nv = W - t;
+                auto keep = [nv](int d) {
+                    return nv >= 2 * d + 2 ? 0xFFFFFFFFu : (nv == 2 * d + 1 ? 0xFFFFu : 0u);
+                };
+                v.x &= keep(0);
+                v.y &= keep(1);
+                v.z &= keep(2);
+                v.w &= keep(3);
+            }
+            in.hv[q] = v;
         } else if (t < W) {
-            // the window's last, partial group (or a hits array that is not
+            // the array's last, partial group (or a hits array that is not
             // 16-byte aligned): word by word, all eight loads in flight at
             // once (indices clamped into the array, which holds at least the
             // window), zeros past the window
@@ -454,15 +467,20 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *s_cd, int32_t s, i
     }
     // the road's rows, in (i_c, i_d) order, at its place in the binned list;
     // each carries its key bits (i_c and i_d at their layers' places)
+    // (the entry is tid + i_c A + i_d B with A, B the place values of i_c
+    // and i_d; after each i_d it steps by B, and after the last i_d of an
+    // i_c by A - (n_d - 1) B)
     if (active && rows) {
-        const uint32_t nd = kd >> 2, sc = 12u - 4u * lc, sd = 12u - 4u * ld;
-        uint32_t w = bstart + boff, ic = 0, id = 0;
-        for (uint32_t k = 0; k < rows; ++k, ++w) {
-            S.row[w] = (uint32_t)tid | (ic << 8) | (id << 12) | (((ic << sc) | (id << sd)) << 16);
-            if (++id == nd) {
-                id = 0;
-                ++ic;
-            }
+        const uint32_t nd = kd >> 2;
+        const uint32_t B = (1u << 12) | (1u << (28u - 4u * ld));
+        const uint32_t wrap = ((1u << 8) | (1u << (28u - 4u * lc))) - nd * B;
+        uint32_t *dst = &S.row[bstart + boff];
+        uint32_t e = (uint32_t)tid, left = nd;
+        for (uint32_t k = 0; k < rows; ++k) {
+            dst[k] = e;
+            --left;
+            e += left ? B : wrap + B;
+            left = left ? left : nd;
         }
     }
     __syncthreads();
