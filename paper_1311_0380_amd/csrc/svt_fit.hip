@@ -1,9 +1,11 @@
 // Fused SVT fit kernel for gfx950 (arXiv:1311.0380, Sec. 2 / Sec. 2.1).
 //
-// One persistent grid.  Work item = a chunk of `events_per_chunk` consecutive
-// events, so every event (and its track count) belongs to exactly one block.
-// A chunk's roads are processed in sub-chunks of at most kSubRoads roads whose
-// hits (kHitCap) and (i0, i1) rows (kRowCap) fit in LDS:
+// Four 256-thread blocks per CU (128 VGPRs, 31 KB of LDS each; the sector
+// constants are read from device memory through the caches).  Work item = a
+// chunk of `events_per_chunk` consecutive events, so every event (and its
+// track count) belongs to exactly one block.  A chunk's roads are processed in
+// sub-chunks of at most kSubRoads roads whose hits (kHitCap) and rows
+// (kRowCap) fit in LDS:
 //
 //   A  one thread per road: load + validate the road, prefix sums give each
 //      road its slot in the LDS hit table and row list.  The road's two
@@ -103,11 +105,9 @@ struct Shared {
     int32_t misc[4];                        // [2]: a staged word is out of range; [3]: rows
 };
 
-// LDS per block: the static part plus the constants image (272 bytes per
-// sector).  Three blocks (twelve wavefronts, the VGPR limit) share a CU's
-// 160 KB up to 72 sectors; LDS is allocated in 512-byte granules.
-static_assert(((sizeof(Shared) + 1024 + 72 * kCstBytesPerSector + 511) / 512) * 512 * 3 <= 160 * 1024,
-              "three blocks per CU at 72 sectors");
+// LDS per block: four blocks (sixteen wavefronts, the VGPR limit at 128)
+// share a CU's 160 KB; LDS is allocated in 512-byte granules.
+static_assert(((sizeof(Shared) + 1024 + 511) / 512) * 512 * 4 <= 160 * 1024, "four blocks per CU");
 
 // OR across the wavefront (all lanes active), as a uniform value.
 __device__ __forceinline__ uint32_t wave_or(uint32_t x)
@@ -329,7 +329,7 @@ __device__ __forceinline__ void window_loads_hits(const FitArgs &a, int32_t hw, 
 // that fit (a prefix of the sub-chunk, at least one when s < rb), and the
 // sub-chunk's rows.
 template <bool F>
-__device__ __forceinline__ int sub_a(Shared &S, const double *s_cd, int32_t s, int32_t rb,
+__device__ __forceinline__ int sub_a(Shared &S, const double *cst, int32_t s, int32_t rb,
                                      int32_t n_roads, int32_t n_hits, int32_t n_sectors,
                                      const SubIn &in, int32_t hw, int32_t W, Acc &acc,
                                      int32_t &total_rows_out)
@@ -430,7 +430,7 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *s_cd, int32_t s, i
         if (rows) boff = atomicAdd(&S.bin[bkey], rows);
         if (ok) {
             // constant part of the constraint rows, exact in int32
-            const double *cs = s_cd + sec * kCstStride;
+            const double *cs = cst + sec * kCstStride;
             const int32_t *cbi = reinterpret_cast<const int32_t *>(cs) + kCstIntB;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -492,7 +492,7 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *s_cd, int32_t s, i
 
 // Phase B: every combination of every row (one thread per row).
 template <bool F>
-__device__ __forceinline__ void sub_b(Shared &S, const double *s_cd, int32_t total_rows, double cut)
+__device__ __forceinline__ void sub_b(Shared &S, const double *cst, int32_t total_rows, double cut)
 {
     const int tid = threadIdx.x;
     const double lim = F ? cut + 0.5 : cut;
@@ -504,8 +504,8 @@ __device__ __forceinline__ void sub_b(Shared &S, const double *s_cd, int32_t tot
         const uint32_t j = d & 255u, ic = (d >> 8) & 15u, id = (d >> 12) & 15u;
         const uint4 ra = S.ra[j];
         const uint32_t shp = S.shape[j];
-        const double *cc = s_cd + (ra.z & 0xFFFFu), *cd = s_cd + (ra.z >> 16);
-        const double *ca = s_cd + (ra.w & 0xFFFFu), *cb = s_cd + (ra.w >> 16);
+        const double *cc = cst + (ra.z & 0xFFFFu), *cd = cst + (ra.z >> 16);
+        const double *ca = cst + (ra.w & 0xFFFFu), *cb = cst + (ra.w >> 16);
         const double hc = (double)S.hit[(ra.x & 0xFFFFu) + ic], hd = (double)S.hit[(ra.x >> 16) + id];
         Row st;
         st.z3 = fma(cd[0], hd, fma(cc[0], hc, (double)S.base[0][j]));
@@ -537,7 +537,7 @@ __device__ __forceinline__ void sub_b(Shared &S, const double *s_cd, int32_t tot
 // Phase C: the results of the sub-chunk's fitted roads [s, s + L) (one
 // thread per road) and their tracks counted per event of the chunk (event
 // road offsets evro, ne events).
-__device__ __forceinline__ void sub_c(const FitArgs &a, Shared &S, const double *s_cd, int32_t s,
+__device__ __forceinline__ void sub_c(const FitArgs &a, Shared &S, const double *cst, int32_t s,
                                       int32_t L, int32_t ne, const int32_t *evro, uint32_t x2,
                                       Acc &acc)
 {
@@ -574,7 +574,7 @@ __device__ __forceinline__ void sub_c(const FitArgs &a, Shared &S, const double 
                                    (uint32_t)(int32_t)S.hit[hp + c0 + c1 + c2n + i3],
                                    (uint32_t)xa, (uint32_t)xb};
             // parameter rows 0..2, exact in int32 by the load-time bound
-            const int32_t *ci = reinterpret_cast<const int32_t *>(s_cd + (inf >> 16) * kCstStride);
+            const int32_t *ci = reinterpret_cast<const int32_t *>(cst + (inf >> 16) * kCstStride);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 uint32_t acc32 = (uint32_t)ci[kCstIntPB + k];
@@ -614,14 +614,10 @@ __device__ __forceinline__ void sub_c(const FitArgs &a, Shared &S, const double 
 
 // Process the roads [s, rb) of the current chunk starting at road s; returns
 // how many roads were fitted (at least one when s < rb).
-//
-// copy_image: the block's first sub-chunk also stages the sector constants
-// image into LDS, issued after its own loads so that the two latencies
-// overlap (the image is first read after the sub-chunk's first barrier).
 template <bool F>
-__device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t s, int32_t rb,
+__device__ int process_sub(const FitArgs &a_in, Shared &S, const double *cst, int32_t s, int32_t rb,
                            int32_t n_roads, int32_t n_hits, int32_t n_sectors, int32_t ne,
-                           double cut, bool vec, bool copy_image, Acc &acc)
+                           double cut, bool vec, Acc &acc)
 {
     const FitArgs &a = fresh_args(a_in);
     const int tid = threadIdx.x;
@@ -631,16 +627,10 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, double *s_cd, int32_t
     road_loads(a, s, rb, in);
     window_of(wraw, n_hits, hw, W);
     window_loads_hits(a, hw, W, n_hits, vec, in);
-    if (copy_image) {
-        const uint4 *csrc = reinterpret_cast<const uint4 *>(a.cst_block);
-        uint4 *cdst = reinterpret_cast<uint4 *>(s_cd);
-        const int n16 = n_sectors * kCstBytesPerSector / 16;
-        for (int i = tid; i < n16; i += kBlock) cdst[i] = csrc[i];
-    }
     int32_t total_rows;
-    const int L = sub_a<F>(S, s_cd, s, rb, n_roads, n_hits, n_sectors, in, hw, W, acc, total_rows);
-    sub_b<F>(S, s_cd, total_rows, cut);
-    sub_c(a, S, s_cd, s, L, ne, S.evro, in.x2, acc);
+    const int L = sub_a<F>(S, cst, s, rb, n_roads, n_hits, n_sectors, in, hw, W, acc, total_rows);
+    sub_b<F>(S, cst, total_rows, cut);
+    sub_c(a, S, cst, s, L, ne, S.evro, in.x2, acc);
     return L;
 }
 
@@ -717,13 +707,10 @@ __device__ __forceinline__ void write_partial(const FitArgs &a, int32_t blk, con
 }
 
 // One block's share of one batch: block blk of the nblk blocks the batch is
-// spread over.  staged: the sector constants image is in LDS already (a
-// block fitting several batches stages it once); set once it is.
-__device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk, const int32_t nblk,
-                                          bool &staged)
+// spread over.
+__device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk, const int32_t nblk)
 {
     const FitArgs &a = fresh_args(a_in);
-    extern __shared__ __align__(16) unsigned char s_dyn[];
     __shared__ __align__(16) Shared S;
     const int tid = threadIdx.x;
 
@@ -743,15 +730,13 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
         seq = *a.seq_dev;
     }
     const int32_t n_sectors = a.n_sectors;
-    double *s_cd = reinterpret_cast<double *>(s_dyn);
+    // the sector constants, read through the caches (device memory)
+    typedef const __attribute__((address_space(1))) double GlobalDouble;
+    const double *cst = (const double *)(GlobalDouble *)a.cst_block;
 
     Acc acc;
     const double cut = a.cut_d;
     const int32_t E = a.events_per_chunk;
-    // sector constants -> LDS: a copy of the image built at load time
-    const uint4 *csrc = reinterpret_cast<const uint4 *>(a.cst_block);
-    uint4 *cdst = reinterpret_cast<uint4 *>(s_cd);
-    const int n16 = n_sectors * kCstBytesPerSector / 16;
 
     int32_t c_first, c_step, c_last;
     // chunk c covers events [e_base + c E, min(e_base + (c + 1) E, e_end))
@@ -781,8 +766,6 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
                                  (e == n_events - 1 && hi != n_roads);
                 if (bad) bad_event = min(bad_event, (uint32_t)e);
             }
-            if (!staged)
-                for (int i = t2; i < n16; i += 128) cdst[i] = csrc[i];
         }
         acc.err_event = min(acc.err_event, wave_min(bad_event));
         __syncthreads();
@@ -797,8 +780,7 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
         chunk_range(n_chunks, a.schedule, blk, nblk, c_first, c_step, c_last);
     }
 
-    // the first chunk's event boundaries are in flight while the sector
-    // constants are staged
+    // the first chunk's event boundaries
     int32_t ev0 = 0, ev1 = 0;
     if (c_first < c_last) {
         const int32_t e0 = e_base + c_first * E, ne = min(E, e_end - e0);
@@ -806,10 +788,6 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
         if (tid + kBlock <= ne) ev1 = a.road_offsets[e0 + tid + kBlock];
     }
 
-    // (with the cyclic and blocked schedules the first sub-chunk stages the
-    // sector constants, see process_sub)
-    if (a.schedule == 3) staged = true;
-    bool copy_image = !staged;
     static_assert(kBins == kBlock, "one bin per thread");
     S.bin[tid] = 0;
     if (tid == 0) S.misc[2] = 0;
@@ -830,10 +808,9 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
         __syncthreads();
         const int32_t ra = clampi(S.evro[0], 0, n_roads);
         const int32_t rb = clampi(S.evro[ne], ra, n_roads);
-        for (int32_t s = ra; s < rb; copy_image = false)
-            s += a.frac_key
-                     ? process_sub<true>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, copy_image, acc)
-                     : process_sub<false>(a, S, s_cd, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, copy_image, acc);
+        for (int32_t s = ra; s < rb;)
+            s += a.frac_key ? process_sub<true>(a, S, cst, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, acc)
+                            : process_sub<false>(a, S, cst, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, acc);
         uint32_t bad_event = 0xFFFFFFFFu;
         for (int i = tid; i < ne; i += kBlock) {
             const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
@@ -845,12 +822,11 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
         acc.err_event = min(acc.err_event, wave_min(bad_event));
         __syncthreads();
     }
-    staged = !copy_image;
 
     write_partial(a, blk, acc, seq);
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 fit_kernel(FitArgs a)
 {
     // the argument is read in place, in the kernel argument segment (where
@@ -858,21 +834,19 @@ fit_kernel(FitArgs a)
     // copied to private memory
     (void)a;
     ConstArgs *pa = (ConstArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-    bool staged = false;
-    fit_block(*(const FitArgs *)pa, (int32_t)blockIdx.x, (int32_t)gridDim.x, staged);
+    fit_block(*(const FitArgs *)pa, (int32_t)blockIdx.x, (int32_t)gridDim.x);
 }
 
 // Several batches in one launch: batch i takes blocks [i per, (i + 1) per),
 // so that blocks of later batches start wherever blocks of earlier ones end.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 fit_kernel_multi(const FitArgs *__restrict__ args, int32_t per)
 {
     const int32_t i = (int32_t)blockIdx.x / per;
     // read through the constant address space: the argument loads can then be
     // repeated where they are used instead of holding every field in registers
     ConstArgs *ca = (ConstArgs *)args;
-    bool staged = false;
-    fit_block(*(const FitArgs *)&ca[i], (int32_t)blockIdx.x - i * per, per, staged);
+    fit_block(*(const FitArgs *)&ca[i], (int32_t)blockIdx.x - i * per, per);
 }
 
 // ---------------------------------------------------------------------------
@@ -944,33 +918,19 @@ __global__ void copy_seq(const uint32_t *src, uint32_t *dst)
 
 }  // namespace
 
-hipError_t prepare_fit()
+hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, hipStream_t stream)
 {
-    const int max_dyn = 256 * kCstBytesPerSector;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(fit_kernel_multi),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_dyn);
-    return e;
-}
-
-hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, size_t dyn_lds,
-                            hipStream_t stream)
-{
-    hipLaunchKernelGGL(fit_kernel_multi, dim3(n_batches * per), dim3(kBlock), dyn_lds, stream, args,
+    hipLaunchKernelGGL(fit_kernel_multi, dim3(n_batches * per), dim3(kBlock), 0, stream, args,
                        (int32_t)per);
     return hipGetLastError();
 }
 
-hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream,
-                      hipEvent_t start, hipEvent_t stop)
+hipError_t launch_fit(const FitArgs &a, int grid, hipStream_t stream, hipEvent_t start, hipEvent_t stop)
 {
     if (start != nullptr || stop != nullptr)
-        hipExtLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), (uint32_t)dyn_lds, stream, start,
-                              stop, 0u, a);
+        hipExtLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), 0u, stream, start, stop, 0u, a);
     else
-        hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), dyn_lds, stream, a);
+        hipLaunchKernelGGL(fit_kernel, dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

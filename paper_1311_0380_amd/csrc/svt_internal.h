@@ -13,9 +13,8 @@ constexpr int kRowCap = 1536;      // rows per sub-chunk (the block kernel's row
 constexpr int kMaxEventsPerChunk = 256;
 constexpr int kMaxBlocksPerCu = 16;
 constexpr int kTargetRoadsPerChunk = 256;
-// Per sector, in dynamic LDS (stride kCstStride doubles = 272 bytes, an odd
-// multiple of 16 so that per-lane 16-byte reads of different sectors spread
-// over the LDS banks):
+// Per sector, in device memory, read by the fit kernel through the caches
+// (stride kCstStride doubles = 272 bytes):
 //   doubles [0, 18)   constraint rows 3..5, 6 columns x 3 rows ([col * 3 + row])
 //   int32   [36, 39)  offsets of rows 3..5
 //   int32   [40, 58)  parameter rows 0..2, 6 columns x 3 rows ([col * 3 + row])
@@ -69,7 +68,7 @@ struct FitArgs {
     int32_t *params;
     uint32_t *hit_index4;       // 4 x uint8 per road
     int32_t *ntracks;
-    const double *cst_block;    // the kernel's LDS image of the constants: [n_sectors][kCstStride]
+    const double *cst_block;    // the kernel's table of the constants: [n_sectors][kCstStride]
     int32_t frac_key;           // 1: cut < 2^44, minimise chi2 + index / 256
     // launch shape
     int32_t events_per_chunk;
@@ -79,15 +78,13 @@ struct FitArgs {
     uint32_t seq;
 };
 
-hipError_t prepare_fit();   // one-time kernel attributes (call outside graph capture)
 // start/stop non-NULL: the dispatch itself records them around the kernel
 // (no separate event packets on the stream).
-hipError_t launch_fit(const FitArgs &a, int grid, size_t dyn_lds, hipStream_t stream,
-                      hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+hipError_t launch_fit(const FitArgs &a, int grid, hipStream_t stream, hipEvent_t start = nullptr,
+                      hipEvent_t stop = nullptr);
 // n_batches batches in one launch of the block kernel: args is device memory
 // holding one FitArgs per batch; batch i is spread over blocks [i per, (i+1) per).
-hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, size_t dyn_lds,
-                            hipStream_t stream);
+hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, hipStream_t stream);
 // One thread copies a request's sequence number from host-mapped memory to
 // device memory (the first node of a ring's graph; the fit kernels then read
 // it from device memory).
