@@ -103,6 +103,7 @@ struct Shared {
     uint32_t wout[kWaves];                  // first lane of each wavefront outside the window
     uint32_t wfit[kWaves];                  // first lane of each wavefront that does not fit
     int32_t misc[4];                        // [2]: a staged word is out of range; [3]: rows
+    uint32_t seq;                           // the request's sequence number
 };
 
 // LDS per block: four blocks (sixteen wavefronts, the VGPR limit at 128)
@@ -423,7 +424,10 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *cst, int32_t s, in
                                (cb + 3u * lc) | ((cb + 3u * ld) << 16),
                                (cb + 3u * la) | ((cb + 3u * lb) << 16));
         S.shape[tid] = (ka >> 2) | ((kb >> 2) << 5) | ((12u - 4u * la) << 10) | ((12u - 4u * lb) << 14);
-        S.key[tid] = ~0ull;
+        // (made here: a constant hoisted out of the chunk loop is spilled)
+        uint32_t none = 0xFFFFFFFFu;
+        asm volatile("" : "+v"(none));
+        S.key[tid] = ((unsigned long long)none << 32) | none;
         S.np[tid] = 0;
         S.n4[tid] = ok ? nh4 : 0u;
         S.info[tid] = (uint32_t)pos | (sec << 16);
@@ -684,7 +688,7 @@ __device__ __forceinline__ void chunk_range(int32_t n_chunks, int32_t schedule, 
 // wave ids are recomputed here rather than kept live across the whole kernel.
 // Every thread calls it (one barrier).
 __device__ __forceinline__ void write_partial(const FitArgs &a, int32_t blk, const Acc &acc,
-                                              uint32_t seq)
+                                              const uint32_t &seq)
 {
     const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
@@ -729,6 +733,9 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     } else if (a.seq_dev != nullptr) {
         seq = *a.seq_dev;
     }
+    // kept in LDS until the block's sums are written (not in a register
+    // across the whole kernel)
+    if (tid == 0) S.seq = seq;
     const int32_t n_sectors = a.n_sectors;
     // the sector constants, read through the caches (device memory)
     typedef const __attribute__((address_space(1))) double GlobalDouble;
@@ -802,8 +809,12 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     for (int32_t c = c_first; c < c_last; c += c_step) {
         const int32_t e0 = e_base + c * E;
         const int32_t ne = min(E, e_end - e0);
-        if (c != c_first)
-            for (int i = tid; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
+        if (c != c_first) {
+            // (an index made here: one carried from chunk to chunk is spilled)
+            int it = tid;
+            asm volatile("" : "+v"(it));
+            for (int i = it; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
+        }
         if (tid < ne) S.evcnt[tid] = 0;   // ne <= kMaxEventsPerChunk = kBlock
         __syncthreads();
         const int32_t ra = clampi(S.evro[0], 0, n_roads);
@@ -812,7 +823,10 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
             s += a.frac_key ? process_sub<true>(a, S, cst, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, acc)
                             : process_sub<false>(a, S, cst, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, acc);
         uint32_t bad_event = 0xFFFFFFFFu;
-        for (int i = tid; i < ne; i += kBlock) {
+        // (the thread's first event made here, not held across the sub-chunks)
+        int i0 = tid;
+        asm volatile("" : "+v"(i0));
+        for (int i = i0; i < ne; i += kBlock) {
             const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
             const bool bad = lo < 0 || hi < lo || hi > n_roads || (e == 0 && lo != 0) ||
                              (e == n_events - 1 && hi != n_roads);
@@ -823,7 +837,7 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
         __syncthreads();
     }
 
-    write_partial(a, blk, acc, seq);
+    write_partial(a, blk, acc, S.seq);
 }
 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
