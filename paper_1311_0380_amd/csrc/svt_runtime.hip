@@ -1225,6 +1225,9 @@ svt_status svt_plan_create(svt_ctx *c, int32_t max_events, int32_t max_roads, in
         if (e == hipSuccess && e2 != hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    // uploaded now, so that the first run does not pay for it
+    if (e == hipSuccess) e = hipGraphUpload(p->exec, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         st = hip_fail(e, "plan capture");
@@ -1486,6 +1489,9 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         if (e == hipSuccess && e2 != hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
+    // uploaded now, so that the first run does not pay for it
+    if (e == hipSuccess) e = hipGraphUpload(r->exec, cs);
+    if (e == hipSuccess) e = hipStreamSynchronize(cs);
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         st = hip_fail(e, "ring capture");
