@@ -16,9 +16,8 @@ struct ListArgs {
     int64_t *offsets;           // out: exclusive running sum of npass, [n_roads + 1]
     const int64_t *tile_excl;   // running sum of npass before each tile of kListTile roads
     int32_t n_roads, n_hits, n_sectors;
-    const int32_t *coef;        // [n_sectors][6][6]
-    const int32_t *offset;      // [n_sectors][6]
-    uint64_t cut;
+    const double *cst;          // the fit kernel's table of the constants: [n_sectors][kCstStride]
+    uint64_t cut;               // < 2^48
     int32_t *k;                 // entries: combination index, chi2, fit rows 0..2
     uint64_t *chi2;
     int32_t *params;
@@ -26,8 +25,7 @@ struct ListArgs {
     BlockPartial *partials;     // host-mapped, [gridDim.x]
     uint32_t seq;
 };
-constexpr int kListRoads = 64;   // roads per block of the list kernel
-constexpr int kListTile = 256;   // roads per tile of its offsets scan
+constexpr int kListTile = 256;   // roads per tile of the offsets scan and per block pass of the list kernel
 size_t list_scratch_bytes(int32_t n_roads);
 // The offsets scan and the list kernel; scratch holds list_scratch_bytes.
 hipError_t launch_list(const ListArgs &a, int grid, int64_t *scratch, hipStream_t stream);

@@ -784,8 +784,7 @@ svt_status list_submit(svt_ctx *c, const svt_event_batch *b, const int32_t *npas
     a.n_roads = nr;
     a.n_hits = nh;
     a.n_sectors = c->n_sectors;
-    a.coef = c->coef;
-    a.offset = c->offset;
+    a.cst = static_cast<const double *>(c->cst_block);
     a.cut = c->cut;
     a.k = list->k;
     a.chi2 = list->chi2;
@@ -794,8 +793,8 @@ svt_status list_submit(svt_ctx *c, const svt_event_batch *b, const int32_t *npas
     a.partials = static_cast<svt::BlockPartial *>(
         const_cast<void *>(device_view(s.partials, SVT_MEM_MAPPED)));
     a.seq = (uint32_t)c->next_ticket;
-    // one block per svt::kListRoads roads, at most the partials' capacity
-    int64_t grid = ((int64_t)nr + svt::kListRoads - 1) / svt::kListRoads;
+    // one block per tile of svt::kListTile roads, at most the partials' capacity
+    int64_t grid = ((int64_t)nr + svt::kListTile - 1) / svt::kListTile;
     if (grid > c->max_grid) grid = c->max_grid;
     if (grid < 1) grid = 1;
 
