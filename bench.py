@@ -440,7 +440,7 @@ def section_list(args, svt, synth, torch):
             "request_device_us_p50": req_s * 1e6, "request_wall_us_p50": pct(wall, 50) * 1e6,
             "entries_per_s": entries / req_s, "algorithmic_bytes": alg,
             "achieved_gbs": alg / req_s / 1e9, "hbm_frac": alg / req_s / 1e9 / HBM_PEAK_GBS,
-            "timed": "events around the request: the offsets scan (two small kernels) "
+            "timed": "events around the request: the tile sums of npass (one small kernel) "
                      "and the list kernel"}
 
 

@@ -14,7 +14,7 @@ struct ListArgs {
     const uint32_t *xft2;
     const int32_t *npass;       // pass counts of the fit, [n_roads]
     int64_t *offsets;           // out: exclusive running sum of npass, [n_roads + 1]
-    const int64_t *tile_excl;   // running sum of npass before each tile of kListTile roads
+    const int64_t *tile_sum;    // npass summed over each tile of kListTile roads
     int32_t n_roads, n_hits, n_sectors;
     const double *cst;          // the fit kernel's table of the constants: [n_sectors][kCstStride]
     uint64_t cut;               // < 2^48

@@ -5,13 +5,14 @@
 //
 // Three kernels on the request's stream:
 // - list_tile_sums: npass summed over tiles of kListTile roads;
-// - list_tile_scan: one block turns the tile sums into a running sum;
-// - list_kernel: a block takes a tile of 256 roads at a time, in sub-chunks
+// - list_kernel: a block takes a tile of 256 roads at a time (the running
+//   sum of npass before it from the tile sums, added up by the block), in
+//   sub-chunks
 //   whose hits and row pieces fit in LDS, one thread per road in phase A and
 //   one per row piece in phase B, as the fit kernel does:
 //   A  each road is loaded and validated as the fit does; its list offset is
 //      the running sum before the tile plus the npass of the tile's earlier
-//      roads, and is written out.  A road to evaluate (valid, npass > 0) is
+//      roads, and is written out (and the list's length after the last road).  A road to evaluate (valid, npass > 0) is
 //      cut into row pieces: (i0, i1) and a run of at most 32 / n3 values of
 //      i2, so that a piece has at most 32 combinations.  The pieces get
 //      places in road order (their combinations then come in combination
@@ -97,36 +98,6 @@ __global__ void __launch_bounds__(kBlock) list_tile_sums(const int32_t *npass, i
     }
 }
 
-// One block: tile sums -> exclusive running sum in place, the total after the
-// last tile and at offsets[n] (the list's length by npass).
-__global__ void __launch_bounds__(kBlock) list_tile_scan(int64_t *tsum, int32_t n_tiles, int64_t *offsets,
-                                                         int32_t n)
-{
-    __shared__ int64_t s_w[kWaves];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int64_t carry = 0;
-    for (int32_t b0 = 0; b0 < n_tiles; b0 += kBlock) {
-        const int32_t b = b0 + threadIdx.x;
-        const int64_t v = b < n_tiles ? tsum[b] : 0;
-        const int64_t incl = wave_incl64(v);
-        if (lane == 63) s_w[wid] = incl;
-        __syncthreads();
-        int64_t before = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            before += w < wid ? s_w[w] : 0;
-            tot += s_w[w];
-        }
-        if (b < n_tiles) tsum[b] = carry + before + incl - v;
-        carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        tsum[n_tiles] = carry;
-        offsets[n] = carry;
-    }
-}
-
 // Row pieces and staged hits of one sub-chunk.
 constexpr int kLHitCap = 4096;                     // hits staged per sub-chunk
 constexpr int kLPieceCap = 2048;                   // row pieces per sub-chunk (>= one road's)
@@ -150,6 +121,7 @@ struct ListShared {
     int32_t base[3][kBlock];       // constraint rows 3..5 at zero hits (offset and XFT columns)
     __align__(16) uint32_t bin[kLBins];   // read four at a time
     uint32_t w[4][kBlock / 64];    // per-wavefront sums of the scans
+    int64_t wt[kBlock / 64];       // per-wavefront sums of tile sums
     int32_t misc[4];
 };
 
@@ -260,10 +232,18 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
     const bool vec = (reinterpret_cast<uintptr_t>(a.hits) & 15u) == 0u;
 
     S.bin[tid] = 0;
+    if (a.n_roads == 0 && blockIdx.x == 0 && tid == 0) a.offsets[0] = 0;
+    // the running sum of npass before a tile: the tile sums before it, which
+    // the block adds up itself (from its previous tile on)
+    int64_t carry = 0, tdone = 0;
     for (int64_t tile = blockIdx.x; tile * kListTile < a.n_roads; tile += gridDim.x) {
         const int32_t t0 = (int32_t)(tile * kListTile);
         const int32_t rb = (int32_t)min((int64_t)a.n_roads, tile * kListTile + kListTile);
-        int64_t obase = a.tile_excl[tile];
+        int64_t tp = 0;
+        for (int64_t t = tdone + tid; t < tile; t += kBlock) tp += a.tile_sum[t];
+        tdone = tile;
+        int64_t obase = carry;   // the tile sums are added at the first sub-chunk
+        bool first = true;
         for (int32_t s = t0; s < rb;) {
             // ---- A: roads, window, pieces ----
             const int32_t r = s + tid;
@@ -321,7 +301,10 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
             const int32_t pos = h0 - hw;
             const bool in_window = !walk || (pos >= 0 && pos + (h1 - h0) <= W);
 
-            // running sums over the sub-chunk's roads: pieces and npass
+            // running sums over the sub-chunk's roads: pieces and npass; the
+            // tile sums before the tile
+            const int64_t tpw = wave_sum64(first ? tp : 0);
+            if (lane == 0) S.wt[wid] = tpw;
             const uint32_t pincl = wave_incl_scan(pieces);
             const uint64_t nincl = (uint64_t)wave_incl64((int64_t)np);
             if (lane == 63) {
@@ -340,6 +323,10 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
             __syncthreads();
             uint32_t pbefore = 0, ptotal = 0, first_out = kBlock;
             uint64_t nbefore = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) obase += S.wt[w];
+            if (first) carry = obase;
+            first = false;
 #pragma unroll
             for (int w = 0; w < kBlock / 64; ++w) {
                 const uint32_t pw = S.w[0][w];
@@ -562,6 +549,7 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
             s += L;
             __syncthreads();
         }
+        if (rb == a.n_roads && tid == 0) a.offsets[a.n_roads] = obase;   // the list's length
     }
 
     // block sums -> host-mapped partials (the host reduces them)
@@ -597,10 +585,8 @@ hipError_t launch_list(const ListArgs &a, int grid, int64_t *scratch, hipStream_
         hipLaunchKernelGGL(list_tile_sums, dim3(tgrid), dim3(kBlock), 0, stream, a.npass, a.n_roads,
                            scratch);
     }
-    hipLaunchKernelGGL(list_tile_scan, dim3(1), dim3(kBlock), 0, stream, scratch, (int32_t)tiles,
-                       a.offsets, a.n_roads);
     ListArgs b = a;
-    b.tile_excl = scratch;
+    b.tile_sum = scratch;
     hipLaunchKernelGGL(list_kernel, dim3(grid), dim3(kBlock), 0, stream, b);
     return hipGetLastError();
 }
