@@ -17,7 +17,7 @@ struct UnpackArgs {
     int32_t copy;               // 1: the first pass copies src into words
     int32_t src_vec, words_vec; // 1: src / words 16-byte aligned (4-word loads)
     int64_t n_words;
-    UnpackAgg *tiles;           // [tiles]: per tile, then the prefix before it
+    UnpackAgg *tiles;           // [tiles]: the sums over each tile
     int32_t *road_offsets;      // outputs, [max_events + 1] ...
     uint8_t *sector;
     uint32_t *nhits4;
@@ -26,7 +26,7 @@ struct UnpackArgs {
     uint32_t *xft2;
     int32_t max_events, max_roads, max_hits;
     int32_t n_apply;            // blocks of the last pass (a grid-stride loop over the
-                                // tiles); the scan's partial follows theirs
+                                // tiles); the totals' partial follows theirs
     BlockPartial *partials;     // host-mapped, [n_apply + 1]
     uint32_t seq;
 };

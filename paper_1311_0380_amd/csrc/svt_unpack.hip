@@ -5,17 +5,18 @@
 // hit words of two hits.
 //
 // Every word's place in the batch follows from counts over the words before
-// it, so the unpack is three data-parallel passes instead of a sequential
+// it, so the unpack is two data-parallel passes instead of a sequential
 // parse:
-//   tile_reduce  per tile of 1024 words: event headers, road headers, hits
+//   tile_reduce  per tile of kTile words: event headers, road headers, hits
 //                declared by road headers, last road header, last event
 //                header (and a copy of the words into device memory when
 //                they are read from host-mapped memory);
-//   tile_scan    one block: the same quantities before each tile, the
-//                totals, the end-of-stream check, the final offsets;
-//   tile_apply   per word: its event / road / hit index from the tile's
-//                prefix plus a block scan, the checks that a sequential
-//                parser would make at that word, and the writes.
+//   tile_apply   per tile, the same quantities before it (the block adds up
+//                the earlier tiles' sums itself); per word, its event / road
+//                / hit index from that plus a block scan, the checks that a
+//                sequential parser would make at that word, and the writes.
+//                The block of the last tile also checks the stream's end and
+//                writes the totals and the final offsets.
 // The first word that breaks the format is the smallest flagged word: up to
 // it the stream is well formed, so every count there equals the parser's.
 #include "svt_unpack.h"
@@ -23,7 +24,10 @@
 namespace svt {
 namespace {
 
-constexpr int kPer = 4;                        // words per thread
+#ifndef SVT_UNPACK_PER
+#define SVT_UNPACK_PER 8
+#endif
+constexpr int kPer = SVT_UNPACK_PER;           // words per thread (16-byte loads of 4)
 constexpr int kTile = kBlock * kPer;           // words per tile
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
@@ -90,22 +94,25 @@ __device__ __forceinline__ Agg wave_incl(Agg v)
     return v;
 }
 
-// the kPer words of a thread: one 16-byte load when aligned and whole
+// the kPer words of a thread: 16-byte loads when aligned and whole
 __device__ __forceinline__ void load_words(const uint32_t *src, int64_t base, int64_t n, bool vec,
                                            uint32_t (&w)[kPer])
 {
     if (vec && base + kPer <= n) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(src + base);
-        w[0] = q.x;
-        w[1] = q.y;
-        w[2] = q.z;
-        w[3] = q.w;
+#pragma unroll
+        for (int v = 0; v < kPer / 4; ++v) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(src + base + 4 * v);
+            w[4 * v + 0] = q.x;
+            w[4 * v + 1] = q.y;
+            w[4 * v + 2] = q.z;
+            w[4 * v + 3] = q.w;
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) w[i] = base + i < n ? src[base + i] : 0u;
     }
 }
-static_assert(kPer == 4, "one 16-byte load per thread");
+static_assert(kPer % 4 == 0, "16-byte loads");
 
 // Exclusive scan of one Agg per thread across a block of NT threads (thread
 // order), and the block total.  A wavefront scan (DPP), then the wavefront
@@ -151,7 +158,10 @@ __global__ void __launch_bounds__(kBlock) tile_reduce(UnpackArgs a)
     load_words(a.src, base, a.n_words, a.src_vec != 0, w);
     if (a.copy) {
         if (a.words_vec && base + kPer <= a.n_words) {
-            *reinterpret_cast<uint4 *>(a.words + base) = make_uint4(w[0], w[1], w[2], w[3]);
+#pragma unroll
+            for (int v = 0; v < kPer / 4; ++v)
+                *reinterpret_cast<uint4 *>(a.words + base + 4 * v) =
+                    make_uint4(w[4 * v], w[4 * v + 1], w[4 * v + 2], w[4 * v + 3]);
         } else {
 #pragma unroll
             for (int i = 0; i < kPer; ++i)
@@ -166,48 +176,30 @@ __global__ void __launch_bounds__(kBlock) tile_reduce(UnpackArgs a)
     if (threadIdx.x == 0) a.tiles[blockIdx.x] = tot;
 }
 
-// One block of kScan threads: tile prefixes (kSeq consecutive tiles per
-// thread, one block scan per kScan * kSeq tiles), totals, the end-of-stream
-// check, final offsets.
-constexpr int kScan = 512;
-constexpr int kSeq = 4;
-__global__ void __launch_bounds__(kScan) tile_scan(UnpackArgs a, int64_t n_tiles)
+// After the last tile (totals over the whole stream): the stream must end
+// where its last road ends (or right after an event header that has no
+// road); the final offsets and the totals (in the partial after the apply
+// blocks').  One thread.
+__device__ void finish_stream(const UnpackArgs &a, const Agg &tot)
 {
-    __shared__ Agg s_w[kScan / 64];
-    Agg carry = kZero;
-    for (int64_t t0 = 0; t0 < n_tiles; t0 += kScan * kSeq) {
-        const int64_t t = t0 + (int64_t)threadIdx.x * kSeq;
-        Agg v[kSeq];
-#pragma unroll
-        for (int i = 0; i < kSeq; ++i) v[i] = t + i < n_tiles ? a.tiles[t + i] : kZero;
-        Agg sum = v[0];
-#pragma unroll
-        for (int i = 1; i < kSeq; ++i) sum = agg_add(sum, v[i]);
-        Agg tot;
-        Agg ex = agg_add(carry, block_excl<kScan>(sum, s_w, tot));
-#pragma unroll
-        for (int i = 0; i < kSeq; ++i) {
-            if (t + i < n_tiles) a.tiles[t + i] = ex;
-            ex = agg_add(ex, v[i]);
-        }
-        carry = agg_add(carry, tot);
+    uint32_t bad = kNone;
+    const int64_t W = a.n_words;
+    if (W > 0) {
+        const int64_t end = tot.last_road > tot.last_ev
+                                ? (int64_t)tot.last_road + road_len(a.words[tot.last_road])
+                                : (int64_t)tot.last_ev + 1;
+        if (end != W) bad = (uint32_t)W;
     }
-    if (threadIdx.x == 0) {
-        // the stream must end where its last road ends (or right after an
-        // event header that has no road)
-        uint32_t bad = kNone;
-        const int64_t W = a.n_words;
-        if (W > 0) {
-            const int64_t end = carry.last_road > carry.last_ev
-                                    ? (int64_t)carry.last_road + road_len(a.words[carry.last_road])
-                                    : (int64_t)carry.last_ev + 1;
-            if (end != W) bad = (uint32_t)W;
-        }
-        if (carry.ev <= a.max_events) a.road_offsets[carry.ev] = (int32_t)carry.rd;
-        if (carry.rd <= a.max_roads) a.hit_offsets[carry.rd] = (int32_t)carry.hits;
-        a.partials[a.n_apply] = BlockPartial{(uint64_t)carry.rd, (uint64_t)carry.hits,
-                                             (uint32_t)carry.ev, bad, kNone, a.seq};
-    }
+    if (tot.ev <= a.max_events) a.road_offsets[tot.ev] = (int32_t)tot.rd;
+    if (tot.rd <= a.max_roads) a.hit_offsets[tot.rd] = (int32_t)tot.hits;
+    a.partials[a.n_apply] = BlockPartial{(uint64_t)tot.rd, (uint64_t)tot.hits, (uint32_t)tot.ev, bad,
+                                         kNone, a.seq};
+}
+
+// An empty stream: its totals and final offsets.
+__global__ void __launch_bounds__(64) stream_empty(UnpackArgs a)
+{
+    if (threadIdx.x == 0) finish_stream(a, kZero);
 }
 
 __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_tiles)
@@ -215,17 +207,27 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_til
     __shared__ Agg s_w[kBlock / 64];
     __shared__ uint32_t s_bad[kBlock / 64];
     uint32_t bad = kNone;
+    // the sums before a tile: the earlier tiles' sums, which the block adds
+    // up itself (from its previous tile on)
+    Agg carry = kZero;
+    int64_t tdone = 0;
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t base = tile * kTile + (int64_t)threadIdx.x * kPer;
     uint32_t w[kPer];
     load_words(a.words, base, a.n_words, a.words_vec != 0, w);
-    const Agg tile_pre = a.tiles[tile];   // in flight with the words
+    Agg part = kZero;
+    for (int64_t t = tdone + threadIdx.x; t < tile; t += kBlock) part = agg_add(part, a.tiles[t]);
+    tdone = tile;
+    carry = agg_add(carry, block_total(part, s_w));
+    __syncthreads();   // s_w is reused below
+    const Agg tile_pre = carry;
     Agg acc = kZero;
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
         if (base + i < a.n_words) acc = agg_add(acc, agg_word(w[i], (int32_t)(base + i)));
     Agg tot;
     Agg pre = agg_add(tile_pre, block_excl<kBlock>(acc, s_w, tot));
+    if (tile == n_tiles - 1 && threadIdx.x == 0) finish_stream(a, agg_add(tile_pre, tot));
     // the header of the last road before the thread's words (one load; the
     // thread's own road headers replace it as they come)
     uint32_t hdr = pre.last_road >= 0 ? a.words[pre.last_road] : 0u;
@@ -311,10 +313,12 @@ int32_t unpack_apply_blocks(int64_t n_words, int max_partials)
 hipError_t launch_unpack(UnpackArgs a, hipStream_t stream)
 {
     const int64_t tiles = unpack_tiles(a.n_words);
-    if (tiles > 0) hipLaunchKernelGGL(tile_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
-    hipLaunchKernelGGL(tile_scan, dim3(1), dim3(kScan), 0, stream, a, tiles);
-    if (tiles > 0 && a.n_apply > 0)
+    if (tiles > 0 && a.n_apply > 0) {
+        hipLaunchKernelGGL(tile_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, stream, a);
         hipLaunchKernelGGL(tile_apply, dim3((unsigned)a.n_apply), dim3(kBlock), 0, stream, a, tiles);
+    } else {
+        hipLaunchKernelGGL(stream_empty, dim3(1), dim3(64), 0, stream, a);
+    }
     return hipGetLastError();
 }
 
