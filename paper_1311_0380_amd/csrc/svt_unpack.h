@@ -10,6 +10,7 @@ struct UnpackAgg {              // over a range of words (positions < 2^31)
     int64_t hits;               // hits the road headers declare
     int32_t ev, rd;             // event headers, road headers
     int32_t last_road, last_ev; // last road / event header, -1 if none
+    uint32_t last_hdr, pad_;    // the last road header's word (0 if none)
 };
 struct UnpackArgs {
     const uint32_t *src;        // the words as given (device-visible)

@@ -43,7 +43,7 @@ __device__ __forceinline__ uint32_t road_hits(uint32_t w)
 // words of a road: header, XFT word, ceil(hits / 2) hit words
 __device__ __forceinline__ int32_t road_len(uint32_t header) { return 2 + (int32_t)(road_hits(header) + 1) / 2; }
 
-constexpr Agg kZero{0, 0, 0, -1, -1};
+constexpr Agg kZero{0, 0, 0, -1, -1, 0u, 0u};
 
 __device__ __forceinline__ Agg agg_word(uint32_t w, int32_t pos)
 {
@@ -54,13 +54,17 @@ __device__ __forceinline__ Agg agg_word(uint32_t w, int32_t pos)
     a.hits = t == 2u ? road_hits(w) : 0;
     a.last_road = t == 2u ? pos : -1;
     a.last_ev = t == 3u ? pos : -1;
+    a.last_hdr = t == 2u ? w : 0u;
+    a.pad_ = 0u;
     return a;
 }
 
+// (positions are distinct, so the later road header's word goes with the
+// larger position whichever side it is on)
 __device__ __forceinline__ Agg agg_add(const Agg &x, const Agg &y)
 {
     return Agg{x.hits + y.hits, x.ev + y.ev, x.rd + y.rd, max(x.last_road, y.last_road),
-               max(x.last_ev, y.last_ev)};
+               max(x.last_ev, y.last_ev), y.last_road > x.last_road ? y.last_hdr : x.last_hdr, 0u};
 }
 
 // Cross-lane moves by DPP for a wavefront inclusive scan: row shifts by 1,
@@ -80,6 +84,8 @@ __device__ __forceinline__ Agg dpp_move(const Agg &v)
     o.rd = __builtin_amdgcn_update_dpp(0, v.rd, CTRL, ROWS, 0xf, false);
     o.last_road = __builtin_amdgcn_update_dpp(-1, v.last_road, CTRL, ROWS, 0xf, false);
     o.last_ev = __builtin_amdgcn_update_dpp(-1, v.last_ev, CTRL, ROWS, 0xf, false);
+    o.last_hdr = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v.last_hdr, CTRL, ROWS, 0xf, false);
+    o.pad_ = 0u;
     return o;
 }
 
@@ -114,26 +120,29 @@ __device__ __forceinline__ void load_words(const uint32_t *src, int64_t base, in
 }
 static_assert(kPer % 4 == 0, "16-byte loads");
 
-// Exclusive scan of one Agg per thread across a block of NT threads (thread
-// order), and the block total.  A wavefront scan (DPP), then the wavefront
-// totals in LDS.
-template <int NT>
-__device__ Agg block_excl(const Agg &v, Agg *s_w, Agg &total)
+// Exclusive scan of v (thread order) with the block total, and the block sum
+// of u, in one round of LDS and barriers.
+__device__ Agg block_excl_and_sum(const Agg &v, const Agg &u, Agg *s_w, Agg *s_u, Agg &total,
+                                  Agg &usum)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const Agg incl = wave_incl(v);
-    if (lane == 63) s_w[wid] = incl;
+    const Agg uincl = wave_incl(u);
+    if (lane == 63) {
+        s_w[wid] = incl;
+        s_u[wid] = uincl;
+    }
     __syncthreads();
-    Agg before = kZero, tot = kZero;
+    Agg before = kZero, tot = kZero, us = kZero;
 #pragma unroll
-    for (int w = 0; w < NT / 64; ++w) {
+    for (int w = 0; w < kBlock / 64; ++w) {
         if (w < wid) before = agg_add(before, s_w[w]);
         tot = agg_add(tot, s_w[w]);
+        us = agg_add(us, s_u[w]);
     }
     __syncthreads();
     total = tot;
-    // exclusive = before + (inclusive of this lane's predecessor; lane 0
-    // receives the identity): DPP wave_shr:1
+    usum = us;
     return agg_add(before, dpp_move<0x138, 0xf>(incl));
 }
 
@@ -186,7 +195,7 @@ __device__ void finish_stream(const UnpackArgs &a, const Agg &tot)
     const int64_t W = a.n_words;
     if (W > 0) {
         const int64_t end = tot.last_road > tot.last_ev
-                                ? (int64_t)tot.last_road + road_len(a.words[tot.last_road])
+                                ? (int64_t)tot.last_road + road_len(tot.last_hdr)
                                 : (int64_t)tot.last_ev + 1;
         if (end != W) bad = (uint32_t)W;
     }
@@ -205,6 +214,7 @@ __global__ void __launch_bounds__(64) stream_empty(UnpackArgs a)
 __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_tiles)
 {
     __shared__ Agg s_w[kBlock / 64];
+    __shared__ Agg s_u[kBlock / 64];
     __shared__ uint32_t s_bad[kBlock / 64];
     uint32_t bad = kNone;
     // the sums before a tile: the earlier tiles' sums, which the block adds
@@ -218,19 +228,19 @@ __global__ void __launch_bounds__(kBlock) tile_apply(UnpackArgs a, int64_t n_til
     Agg part = kZero;
     for (int64_t t = tdone + threadIdx.x; t < tile; t += kBlock) part = agg_add(part, a.tiles[t]);
     tdone = tile;
-    carry = agg_add(carry, block_total(part, s_w));
-    __syncthreads();   // s_w is reused below
-    const Agg tile_pre = carry;
     Agg acc = kZero;
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
         if (base + i < a.n_words) acc = agg_add(acc, agg_word(w[i], (int32_t)(base + i)));
-    Agg tot;
-    Agg pre = agg_add(tile_pre, block_excl<kBlock>(acc, s_w, tot));
+    Agg tot, psum;
+    const Agg ex = block_excl_and_sum(acc, part, s_w, s_u, tot, psum);
+    carry = agg_add(carry, psum);
+    const Agg tile_pre = carry;
+    Agg pre = agg_add(tile_pre, ex);
     if (tile == n_tiles - 1 && threadIdx.x == 0) finish_stream(a, agg_add(tile_pre, tot));
-    // the header of the last road before the thread's words (one load; the
-    // thread's own road headers replace it as they come)
-    uint32_t hdr = pre.last_road >= 0 ? a.words[pre.last_road] : 0u;
+    // the header of the last road before the thread's words (the thread's
+    // own road headers replace it as they come)
+    uint32_t hdr = pre.last_hdr;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
         const int64_t p = base + i;
