@@ -91,7 +91,7 @@ def _corrupt(words, rng, how):
 
 @pytest.mark.parametrize("how", ["retag", "drop", "insert", "reserved", "truncate"])
 def test_first_bad_word_across_tiles(ctx, oracle_lib, how):
-    """Corruptions anywhere in a stream of many 1024-word tiles: the lowest
+    """Corruptions anywhere in a stream of many 2048-word tiles: the lowest
     flagged word equals the sequential parser's first failure."""
     from paper_1311_0380_amd import svt
     batch, _ = synth.cfg2(n_events=300)
@@ -183,17 +183,21 @@ def test_invalid_calls(ctx):
 
 
 def test_large_stream_grid_stride(ctx, oracle_lib):
-    """More tiles than the last pass has blocks (each block then loops over
-    several tiles): 10,000 events of 64 roads, 4.6 M words."""
-    batch, _ = synth.cfg2(n_events=10000)
+    """More tiles than the last pass has blocks (4,095 at most: each block
+    then loops over several tiles, carrying the sums before them): 20,000
+    events of 64 roads, 9.3 M words in 2048-word tiles."""
+    batch, _ = synth.cfg2(n_events=20000)
     words = synth.pack_stream(batch)
-    assert len(words) > 4096 * 1024
+    assert len(words) > 4096 * 2048
     st, summ, got = ctx.unpack_stream(put(words, 3), mem_kind=3)
     assert st == 0 and summ.total_comb == batch.n_roads
     same_arrays(got, batch)
     # and a bad word in the last tiles
+    # (a hit word: bit 29 is reserved there, while in a road header it is
+    # part of the sector)
     w = words.copy()
-    w[len(w) - 100] |= np.uint32(1 << 29)
+    pos = max(i for i in range(len(w) - 200, len(w)) if (int(w[i]) >> 30) == 0)
+    w[pos] |= np.uint32(1 << 29)
     rc, _, _, bad = oracle_lib.unpack_stream(w)
     st, summ, _ = ctx.unpack_stream(put(w, 3), mem_kind=3)
     assert rc != 0 and summ.err_road == bad
