@@ -3,34 +3,35 @@
 // within the chi2 cut, with its fit rows, instead of only the best of its
 // road).
 //
-// Three kernels on the request's stream:
+// Two kernels on the request's stream:
 // - list_tile_sums: npass summed over tiles of kListTile roads;
 // - list_kernel: a block takes a tile of 256 roads at a time (the running
-//   sum of npass before it from the tile sums, added up by the block), in
-//   sub-chunks
-//   whose hits and row pieces fit in LDS, one thread per road in phase A and
-//   one per row piece in phase B, as the fit kernel does:
+//   sum of npass before it is the tile sums before it, which the block adds
+//   up itself), in sub-chunks whose hits and row pieces fit in LDS, one
+//   thread per road in phase A and one per row piece in phase B, as the fit
+//   kernel does:
 //   A  each road is loaded and validated as the fit does; its list offset is
 //      the running sum before the tile plus the npass of the tile's earlier
-//      roads, and is written out (and the list's length after the last road).  A road to evaluate (valid, npass > 0) is
-//      cut into row pieces: (i0, i1) and a run of at most 32 / n3 values of
-//      i2, so that a piece has at most 32 combinations.  The pieces get
-//      places in road order (their combinations then come in combination
-//      order) and in a list binned by (n3, piece length), which gives the
-//      lanes of a wavefront the same trip counts; the sub-chunk's hits are
-//      staged in LDS.
-//   B  one lane per piece: its combinations' constraint rows and chi2 in
-//      fp64, exact as in the fit (every value is an integer below 2^53
-//      whenever chi2 <= cut < 2^48), and a 32-bit mask of the passing ones
-//      in combination order, stored at the piece's place in road order.
+//      roads, and is written out (and the list's length after the last
+//      road).  A road to evaluate (valid, npass > 0) is cut into row pieces:
+//      (i0, i1) and a run of at most 32 / n3 values of i2, so that a piece
+//      has at most 32 combinations.  The pieces get places in road order
+//      (their combinations then come in combination order) and in a list
+//      binned by (n3, piece length), which gives the lanes of a wavefront
+//      the same trip counts; the sub-chunk's hits are staged in LDS.
+//   B  one lane per piece (two pieces per thread at a time, so that their
+//      loads overlap): its combinations' constraint rows and chi2 in fp64,
+//      exact as in the fit (every value is an integer below 2^53 whenever
+//      chi2 <= cut < 2^48), and a 32-bit mask of the passing ones in
+//      combination order, stored at the piece's place in road order.
 //   S  the masks' counts are scanned in road order: a piece's passing
 //      combinations come after those of every piece before it, so entry e of
 //      the sub-chunk is a piece (a binary search over the scan) and a bit of
 //      its mask (a select over popcounts); each road's count is checked
 //      against its npass.
-//   W  thread t writes entries t, t + 256, ...: the combination index, chi2
-//      and fit rows 0..2, exact in integers; consecutive entries go to
-//      consecutive places in the list.
+//   W  thread t writes entries t, t + 256, ... (four at a time): the
+//      combination index, chi2 and fit rows 0..2, exact in integers;
+//      consecutive entries go to consecutive places in the list.
 // A road whose count of passing combinations differs from its npass, or
 // whose npass is negative, is reported as a bad road; its entries past its
 // npass are not written.
@@ -122,7 +123,6 @@ struct ListShared {
     __align__(16) uint32_t bin[kLBins];   // read four at a time
     uint32_t w[4][kBlock / 64];    // per-wavefront sums of the scans
     int64_t wt[kBlock / 64];       // per-wavefront sums of tile sums
-    int32_t misc[4];
 };
 
 static_assert(offsetof(ListShared, bin) % 16 == 0 && offsetof(ListShared, hit) % 16 == 0,
