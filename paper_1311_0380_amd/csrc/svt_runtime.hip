@@ -16,6 +16,7 @@
 #include "svt_internal.h"
 #include "svt_list.h"
 #include "svt_unpack.h"
+#include "svt_partials.h"
 #include "svt_shadow.h"
 #include "svt_submit_guard.h"
 
@@ -150,7 +151,9 @@ struct svt_ring {
     int32_t n_batches = 0, n_passes = 0;
     int32_t per_launch = 1;                 // passes per kernel launch
     int total_parts = 0;                    // block partials of all passes
-    svt::BlockPartial *partials = nullptr;  // host-mapped [total_parts], pass after pass
+    svt::BlockPartial *parts_dev = nullptr; // device [total_parts], pass after pass
+    svt::BlockPartial *mid_dev = nullptr;   // device: the first reduction pass's partials
+    svt::BlockPartial *summary = nullptr;   // host-mapped: the run's reduced partial
     uint32_t *seq_host = nullptr;           // host-mapped: the run's ticket
     uint32_t *seq_dev = nullptr;            // device copy the fit kernels read
     svt::FitArgs *args_dev = nullptr;       // device: the launch arguments of every pass
@@ -1348,8 +1351,10 @@ static void ring_free(svt_ring *r)
     if (r->graph) (void)hipGraphDestroy(r->graph);
     if (r->seq_dev) dev_free(r->ctx, r->seq_dev, 256);
     if (r->args_dev) dev_free(r->ctx, r->args_dev, r->args_bytes);
+    if (r->parts_dev) dev_free(r->ctx, r->parts_dev, sizeof(svt::BlockPartial) * r->total_parts);
+    if (r->mid_dev) dev_free(r->ctx, r->mid_dev, sizeof(svt::BlockPartial) * svt::kPartialRedBlocks);
     if (r->seq_host) (void)hipHostFree(r->seq_host);
-    if (r->partials) (void)hipHostFree(r->partials);
+    if (r->summary) (void)hipHostFree(r->summary);
     delete r;
 }
 
@@ -1406,13 +1411,23 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     for (int p = 0; p < n_passes; ++p)
         part_off[p + 1] = part_off[p] + (k > 1 ? launch_per[p / k] : shapes[p % n_batches].grid);
     r->total_parts = part_off[n_passes];
+    // the blocks' partials stay in device memory and are reduced there (by
+    // the last two nodes of the graph) into one host-mapped summary
     svt_status st = dev_alloc(c, reinterpret_cast<void **>(&r->seq_dev), 256);
     if (st != SVT_OK) {
         delete r;
         return st;
     }
-    if (hipHostMalloc(reinterpret_cast<void **>(&r->partials),
-                      sizeof(svt::BlockPartial) * r->total_parts,
+    st = dev_alloc(c, reinterpret_cast<void **>(&r->parts_dev),
+                   sizeof(svt::BlockPartial) * r->total_parts);
+    if (st == SVT_OK)
+        st = dev_alloc(c, reinterpret_cast<void **>(&r->mid_dev),
+                       sizeof(svt::BlockPartial) * svt::kPartialRedBlocks);
+    if (st != SVT_OK) {
+        ring_free(r);
+        return st;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&r->summary), sizeof(svt::BlockPartial),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&r->seq_host), 64,
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
@@ -1420,10 +1435,11 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         ring_free(r);
         return st;
     }
-    memset(r->partials, 0, sizeof(svt::BlockPartial) * r->total_parts);
+    memset(r->summary, 0, sizeof(svt::BlockPartial));
     *r->seq_host = 0;
-    svt::BlockPartial *parts_dev = static_cast<svt::BlockPartial *>(
-        const_cast<void *>(device_view(r->partials, SVT_MEM_MAPPED)));
+    svt::BlockPartial *parts_dev = r->parts_dev;
+    svt::BlockPartial *summary_dev = static_cast<svt::BlockPartial *>(
+        const_cast<void *>(device_view(r->summary, SVT_MEM_MAPPED)));
     const uint32_t *seq_src =
         static_cast<const uint32_t *>(device_view(r->seq_host, SVT_MEM_MAPPED));
 
@@ -1471,7 +1487,8 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         }
     }
 
-    // the graph: the run's ticket into device memory, then the launches in order
+    // the graph: the run's ticket into device memory, the launches in order,
+    // then the reduction of their partials
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1484,6 +1501,9 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
             else
                 e2 = launch_shaped(c, args[p0], shapes[p0 % n_batches], cs);
         }
+        if (e2 == hipSuccess)
+            e2 = svt::launch_reduce_partials(parts_dev, r->total_parts, r->mid_dev, summary_dev,
+                                             r->seq_dev, cs);
         e = hipStreamEndCapture(cs, &r->graph);
         if (e == hipSuccess && e2 != hipSuccess) e = e2;
     }
@@ -1524,8 +1544,8 @@ svt_status svt_ring_run(svt_ring *r, void *hip_stream, svt_ticket *ticket)
     s.timed = true;
     s.busy = true;
     s.ticket = c->next_ticket++;
-    s.parts = r->partials;
-    s.grid = r->total_parts;
+    s.parts = r->summary;   // the graph reduced the blocks' partials into it
+    s.grid = 1;
     s.plan = nullptr;
     s.ring = r;
     r->busy = true;
