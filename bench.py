@@ -245,7 +245,9 @@ def section_fit(args, svt, synth, torch):
                   "passes_per_launch": per_launch, "timed_launches": launches,
                   "kernel_us_basis": "device time of the timed graph launches (events around each "
                                      "graph launch on its stream) / kernel launches: back-to-back "
-                                     "fit kernels on one stream, the gaps between them included"},
+                                     "fit kernels on one stream, the gaps between them and the "
+                                     "two small kernels that reduce each graph's block partials "
+                                     "included"},
         requests=requests, batch=batch, consts=consts)
     ctx.close()
     return out
