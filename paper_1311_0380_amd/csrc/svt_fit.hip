@@ -1,7 +1,10 @@
 // Fused SVT fit kernel for gfx950 (arXiv:1311.0380, Sec. 2 / Sec. 2.1).
 //
-// Four 256-thread blocks per CU (128 VGPRs, 31 KB of LDS each; the sector
-// constants are read from device memory through the caches).  Work item = a
+// Five 256-thread blocks per CU (96 VGPRs and no spills, 31 KB of LDS each;
+// the sector constants are read from device memory through the caches).
+// Values the compiler would hoist out of the chunk loop and hold (and spill
+// at 96 VGPRs) are made where they are used: the thread's index through
+// fresh_tid, the cut's limits, the chunk's event indices.  Work item = a
 // chunk of `events_per_chunk` consecutive events, so every event (and its
 // track count) belongs to exactly one block.  A chunk's roads are processed in
 // sub-chunks of at most kSubRoads roads whose hits (kHitCap) and rows
@@ -23,8 +26,9 @@
 //   C  one thread per road: decode the winner, recompute its parameter rows
 //      0..2 exactly in int32, write the road's results, count tracks per event.
 //
-// Each block writes its partial sums to host-mapped memory; the host reduces
-// them when the request completes.
+// Each block writes its partial sums to the request's partials (host-mapped
+// for a request, device memory reduced on the device for a ring); the host
+// reads them when the request completes.
 #include <hip/hip_ext.h>
 
 #include "svt_internal.h"
@@ -32,6 +36,17 @@
 
 namespace svt {
 namespace {
+// The thread's index through a value the compiler cannot see through, so
+// that values derived from it are made where used, not hoisted and held.
+__device__ __forceinline__ int fresh_tid()
+{
+    // the wavefront's index is uniform (a scalar register); the lane's
+    // index is made anew, so no vector register holds the thread's index
+    const int wid = (int)(__builtin_amdgcn_readfirstlane(threadIdx.x) >> 6);
+    int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    asm volatile("" : "+v"(lane));
+    return wid * 64 + lane;
+}
 
 constexpr int kBins = 16 * 16;   // inner trip counts (n_a, n_b), each 1..16
 constexpr int kWaves = kBlock / 64;
@@ -93,6 +108,7 @@ struct Shared {
     uint32_t np[kSubRoads];                 // passing combinations of each road
     uint32_t n4[kSubRoads];                 // hit counts of each road (0 if malformed)
     uint32_t info[kSubRoads];               // window position of its first hit | sector << 16
+    uint32_t x2[kSubRoads];                 // the road's XFT words
     // rows, binned by (n_b, n_a): road | i_c << 8 | i_d << 12 | the row's key bits << 16
     uint32_t row[kRowCap];
     __align__(16) int16_t hit[kHitCap + 16];   // staged hit window (+ pad read by row loops)
@@ -106,9 +122,11 @@ struct Shared {
     uint32_t seq;                           // the request's sequence number
 };
 
-// LDS per block: four blocks (sixteen wavefronts, the VGPR limit at 128)
-// share a CU's 160 KB; LDS is allocated in 512-byte granules.
-static_assert(((sizeof(Shared) + 1024 + 511) / 512) * 512 * 4 <= 160 * 1024, "four blocks per CU");
+// LDS per block (Shared and write_partial's per-wavefront partials): five
+// blocks (twenty wavefronts, the VGPR limit at 96) share a CU's 160 KB; LDS
+// is allocated in 512-byte granules.
+static_assert(((sizeof(Shared) + sizeof(BlockPartial) * kWaves + 511) / 512) * 512 * 5 <= 160 * 1024,
+              "five blocks per CU");
 
 // OR across the wavefront (all lanes active), as a uniform value.
 __device__ __forceinline__ uint32_t wave_or(uint32_t x)
@@ -250,7 +268,7 @@ struct SubIn {
 // that nothing waits for them before window_of reads them.
 __device__ __forceinline__ int32_t window_loads(const FitArgs &a, int32_t s, int32_t rb)
 {
-    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int lane = fresh_tid() & 63;
     const int32_t s_end = min(rb, s + kSubRoads);
     return a.hit_offsets[lane == 1 ? s_end : (lane == 2 ? s + 1 : s)];
 }
@@ -266,7 +284,7 @@ __device__ __forceinline__ void window_of(int32_t raw, int32_t n_hits, int32_t &
 // The words of road s + tid (zeros past rb).
 __device__ __forceinline__ void road_loads(const FitArgs &a, int32_t s, int32_t rb, SubIn &in)
 {
-    const int32_t r = s + (int32_t)threadIdx.x;
+    const int32_t r = s + (int32_t)fresh_tid();
     in.sec = 0;
     in.nh4 = 0;
     in.x2 = 0;
@@ -285,7 +303,7 @@ __device__ __forceinline__ void road_loads(const FitArgs &a, int32_t s, int32_t 
 __device__ __forceinline__ void window_loads_hits(const FitArgs &a, int32_t hw, int32_t W, int32_t n_hits,
                                                   bool vec, SubIn &in)
 {
-    const int tid = threadIdx.x;
+    const int tid = fresh_tid();
 #pragma unroll
     for (int q = 0; q < kVecsPerThread; ++q) {
         int32_t t = 8 * (tid + q * kBlock);
@@ -335,7 +353,7 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *cst, int32_t s, in
                                      const SubIn &in, int32_t hw, int32_t W, Acc &acc,
                                      int32_t &total_rows_out)
 {
-    const int tid = threadIdx.x;
+    const int tid = fresh_tid();
     const int lane = tid & 63, wid = tid >> 6;
     const int32_t r = s + tid;
     const bool inr = r < rb;
@@ -431,6 +449,7 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *cst, int32_t s, in
         S.np[tid] = 0;
         S.n4[tid] = ok ? nh4 : 0u;
         S.info[tid] = (uint32_t)pos | (sec << 16);
+        S.x2[tid] = x2;
         if (rows) boff = atomicAdd(&S.bin[bkey], rows);
         if (ok) {
             // constant part of the constraint rows, exact in int32
@@ -491,14 +510,17 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *cst, int32_t s, in
     S.bin[tid] = 0;   // ready for the next sub-chunk (kBins == kBlock)
     if (tid == 0) S.misc[2] = 0;
     total_rows_out = total_rows;
-    return L;
+    return __builtin_amdgcn_readfirstlane(L);
 }
 
 // Phase B: every combination of every row (one thread per row).
 template <bool F>
 __device__ __forceinline__ void sub_b(Shared &S, const double *cst, int32_t total_rows, double cut)
 {
-    const int tid = threadIdx.x;
+    const int tid = fresh_tid();
+    // (the cut through an opaque copy: limits made here, not held from the
+    // kernel's start)
+    asm volatile("" : "+v"(cut));
     const double lim = F ? cut + 0.5 : cut;
     for (int idx0 = 0; idx0 < total_rows; idx0 += kBlock) {
         if (idx0 + (tid & ~63) >= total_rows) continue;   // whole wavefront idle
@@ -542,12 +564,12 @@ __device__ __forceinline__ void sub_b(Shared &S, const double *cst, int32_t tota
 // thread per road) and their tracks counted per event of the chunk (event
 // road offsets evro, ne events).
 __device__ __forceinline__ void sub_c(const FitArgs &a, Shared &S, const double *cst, int32_t s,
-                                      int32_t L, int32_t ne, const int32_t *evro, uint32_t x2,
-                                      Acc &acc)
+                                      int32_t L, int32_t ne, const int32_t *evro, Acc &acc)
 {
-    const int tid = threadIdx.x;
+    const int tid = fresh_tid();
     const int32_t r = s + tid;
     const bool active = tid < L;
+    const uint32_t x2 = active ? S.x2[tid] : 0u;
     const int32_t xa = (int16_t)(x2 & 0xFFFFu), xb = (int16_t)(x2 >> 16);
     // Each road's counts, first hit and sector come back from LDS (zero
     // counts for a malformed road give the same outputs as the road's error
@@ -624,7 +646,7 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, const double *cst, in
                            double cut, bool vec, Acc &acc)
 {
     const FitArgs &a = fresh_args(a_in);
-    const int tid = threadIdx.x;
+    const int tid = fresh_tid();
     int32_t hw, W;
     const int32_t wraw = window_loads(a, s, rb);
     SubIn in;
@@ -634,7 +656,7 @@ __device__ int process_sub(const FitArgs &a_in, Shared &S, const double *cst, in
     int32_t total_rows;
     const int L = sub_a<F>(S, cst, s, rb, n_roads, n_hits, n_sectors, in, hw, W, acc, total_rows);
     sub_b<F>(S, cst, total_rows, cut);
-    sub_c(a, S, cst, s, L, ne, S.evro, in.x2, acc);
+    sub_c(a, S, cst, s, L, ne, S.evro, acc);
     return L;
 }
 
@@ -716,7 +738,6 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
 {
     const FitArgs &a = fresh_args(a_in);
     __shared__ __align__(16) Shared S;
-    const int tid = threadIdx.x;
 
     // sizes and sequence number: from the launch arguments, or read once per
     // block from the plan's host-mapped descriptor (all four words in one
@@ -735,7 +756,7 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     }
     // kept in LDS until the block's sums are written (not in a register
     // across the whole kernel)
-    if (tid == 0) S.seq = seq;
+    if (fresh_tid() == 0) S.seq = seq;
     const int32_t n_sectors = a.n_sectors;
     // the sector constants, read through the caches (device memory)
     typedef const __attribute__((address_space(1))) double GlobalDouble;
@@ -763,9 +784,9 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
             const int64_t bb = b + wid;
             const int32_t e = bb >= G ? n_events
                                       : first_event_at(a.road_offsets, n_events, (int64_t)n_roads * bb / G);
-            if (tid == wid * 64) S.misc[wid] = e;
+            if (fresh_tid() == wid * 64) S.misc[wid] = e;
         } else {
-            const int t2 = tid - 128;
+            const int t2 = fresh_tid() - 128;
             const int32_t per = (int32_t)((n_events + G - 1) / G);
             for (int32_t e = (int32_t)(b * per) + t2; e < min((int64_t)n_events, (b + 1) * per); e += 128) {
                 const int32_t lo = a.road_offsets[e], hi = a.road_offsets[e + 1];
@@ -791,18 +812,20 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     int32_t ev0 = 0, ev1 = 0;
     if (c_first < c_last) {
         const int32_t e0 = e_base + c_first * E, ne = min(E, e_end - e0);
+        const int tid = fresh_tid();
         if (tid <= ne) ev0 = a.road_offsets[e0 + tid];
         if (tid + kBlock <= ne) ev1 = a.road_offsets[e0 + tid + kBlock];
     }
 
     static_assert(kBins == kBlock, "one bin per thread");
-    S.bin[tid] = 0;
-    if (tid == 0) S.misc[2] = 0;
+    S.bin[fresh_tid()] = 0;
+    if (fresh_tid() == 0) S.misc[2] = 0;
     // 16-byte hit loads need a 16-byte aligned hits array
     const bool vec = (reinterpret_cast<uintptr_t>(a.hits) & 15u) == 0u;
 
     if (c_first < c_last) {
         const int32_t ne = min(E, e_end - (e_base + c_first * E));
+        const int tid = fresh_tid();
         if (tid <= ne) S.evro[tid] = ev0;
         if (tid + kBlock <= ne) S.evro[tid + kBlock] = ev1;
     }
@@ -811,11 +834,10 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
         const int32_t ne = min(E, e_end - e0);
         if (c != c_first) {
             // (an index made here: one carried from chunk to chunk is spilled)
-            int it = tid;
-            asm volatile("" : "+v"(it));
+            const int it = fresh_tid();
             for (int i = it; i <= ne; i += kBlock) S.evro[i] = a.road_offsets[e0 + i];
         }
-        if (tid < ne) S.evcnt[tid] = 0;   // ne <= kMaxEventsPerChunk = kBlock
+        if (fresh_tid() < ne) S.evcnt[fresh_tid()] = 0;   // ne <= kMaxEventsPerChunk = kBlock
         __syncthreads();
         const int32_t ra = clampi(S.evro[0], 0, n_roads);
         const int32_t rb = clampi(S.evro[ne], ra, n_roads);
@@ -824,8 +846,7 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
                             : process_sub<false>(a, S, cst, s, rb, n_roads, n_hits, n_sectors, ne, cut, vec, acc);
         uint32_t bad_event = 0xFFFFFFFFu;
         // (the thread's first event made here, not held across the sub-chunks)
-        int i0 = tid;
-        asm volatile("" : "+v"(i0));
+        const int i0 = fresh_tid();
         for (int i = i0; i < ne; i += kBlock) {
             const int32_t e = e0 + i, lo = S.evro[i], hi = S.evro[i + 1];
             const bool bad = lo < 0 || hi < lo || hi > n_roads || (e == 0 && lo != 0) ||
@@ -840,7 +861,7 @@ __device__ __forceinline__ void fit_block(const FitArgs &a_in, const int32_t blk
     write_partial(a, blk, acc, S.seq);
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 fit_kernel(FitArgs a)
 {
     // the argument is read in place, in the kernel argument segment (where
@@ -853,7 +874,7 @@ fit_kernel(FitArgs a)
 
 // Several batches in one launch: batch i takes blocks [i per, (i + 1) per),
 // so that blocks of later batches start wherever blocks of earlier ones end.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
 fit_kernel_multi(const FitArgs *__restrict__ args, int32_t per)
 {
     const int32_t i = (int32_t)blockIdx.x / per;

@@ -302,11 +302,11 @@ int block_roads_per_chunk(int32_t n_roads, int32_t n_hits, int64_t slots)
 
 // Chunking and grid of a launch of the fit kernel (a chunk per block).  A
 // persistent grid (graph plans) keeps the full size; otherwise the grid
-// shrinks to the number of chunks.  Four blocks are resident per CU, but the
+// shrinks to the number of chunks.  Five blocks are resident per CU, but the
 // chunks are sized for three: fuller sub-chunks cost less per road, and the
-// fourth slot is filled by the blocks of the next pass or request (one
-// 3000 x 64-road pass alone: 15.9 us against 15.5 with chunks sized for four;
-// back to back: 10.0 us against 11.4).
+// other slots are filled by the blocks of the next pass or request (with
+// four resident blocks, one 3000 x 64-road pass alone: 15.9 us against 15.5
+// with chunks sized for four; back to back: 10.0 us against 11.4).
 struct LaunchShape {
     int epc;      // events per chunk
     int grid;
@@ -316,7 +316,7 @@ LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int3
                          bool persistent)
 {
     LaunchShape ls;
-    const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 4;
+    const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 5;
     const int sizing = t.blocks_per_cu > 0 ? t.blocks_per_cu : 3;
     ls.epc = t.events_per_chunk > 0
                  ? t.events_per_chunk

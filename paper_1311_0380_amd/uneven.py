@@ -20,7 +20,7 @@ CACHE_PATH = os.environ.get(
                  "svt_tune.json"))
 
 
-CACHE_VERSION = "shapes6"     # bump when the candidate set or the kernels change
+CACHE_VERSION = "shapes7"     # bump when the candidate set or the kernels change
 
 
 def workload_signature(n_events, n_roads, n_hits, ncomb_total=None):
@@ -40,10 +40,10 @@ def candidates(n_events, n_roads):
     out = []
     for e in (1, 2, 4, 8, 16, 32, 64, 128, 256):
         if 128 <= e * rpe <= 512 or (e == 1 and rpe > 512):
-            for bpc in (3, 4):
+            for bpc in (3, 4, 5):
                 for sch in (1, 2):
                     out.append(dict(events_per_chunk=e, blocks_per_cu=bpc, schedule=sch, kernel=1))
-    for bpc in (3, 4):
+    for bpc in (3, 4, 5):
         out.append(dict(events_per_chunk=256, blocks_per_cu=bpc, schedule=3, kernel=1))
     return out
 
