@@ -14,9 +14,9 @@
 //      road its slot in the LDS hit table and row list.  The road's two
 //      layers with the fewest hits index its rows (c, d) and the other two
 //      (a, b) are looped over inside each row, which gives the fewest and
-//      longest rows.  Rows are binned by (n_a, n_b) so that a wavefront's
-//      rows share their inner trip counts; the hits are staged in LDS
-//      (coalesced, flattened); the constraint rows' constant part
+//      longest rows.  Rows are binned by (n_b, n_a), largest first, so that
+//      a wavefront's rows share their inner trip counts; the hits are staged
+//      in LDS (coalesced, flattened); the constraint rows' constant part
 //      b + A[:,4] x4 + A[:,5] x5 is formed.
 //   B  one thread per row (i_c, i_d): z = base + A[:,c] h_c + A[:,d] h_d,
 //      then every (i_a, i_b) combination in the row loops of svt_rows.h.
@@ -180,9 +180,9 @@ __device__ __forceinline__ void frac_small_masked(Row &st, const int16_t *hit, u
     }
 }
 
-// The row loops of one wavefront: its rows are sorted by (n3, n2), so when
-// every lane has the same n3 the last lane holds the largest n2; otherwise
-// the largest of each comes from one OR of one-hot bits.
+// The row loops of one wavefront: its rows are sorted by (n3, n2), largest
+// first, so when every lane has the same n3 the first lane holds the largest
+// n2; otherwise the largest of each comes from one OR of one-hot bits.
 template <bool F>
 __device__ __forceinline__ void run_rows(Row &st, const int16_t *hit, uint32_t p2, uint32_t p3,
                                          uint32_t rn2, uint32_t rn3, double lim)
@@ -190,7 +190,7 @@ __device__ __forceinline__ void run_rows(Row &st, const int16_t *hit, uint32_t p
     const uint32_t n3f = __builtin_amdgcn_readfirstlane(rn3);
     const uint32_t n3l = __builtin_amdgcn_readlane(rn3, 63);
     const bool uni = n3f == n3l;
-    uint32_t n2m = __builtin_amdgcn_readlane(rn2, 63), n3m = n3l;
+    uint32_t n2m = __builtin_amdgcn_readfirstlane(rn2), n3m = n3f;
     if (!uni) {
         const uint32_t m = wave_or((1u << (rn2 - 1u)) | (1u << (rn3 + 15u)));
         n2m = 32u - (uint32_t)__builtin_clz((m & 0xFFFFu) | 1u);
@@ -430,7 +430,10 @@ __device__ __forceinline__ int sub_a(Shared &S, const double *cst, int32_t s, in
     if (tid == L - 1) S.misc[3] = (int32_t)(rbase + rows);    // rows of the sub-chunk
 
     const uint32_t lc = kc & 3u, ld = kd & 3u, la = ka & 3u, lb = kb & 3u;
-    const uint32_t bkey = ((kb >> 2) - 1u) * 16u + ((ka >> 2) - 1u);
+    // bins in descending (n_b, n_a): the largest rows come first, and the
+    // last, partial pass over the row list (which one wavefront runs while
+    // the others wait at the barrier) takes the smallest
+    const uint32_t bkey = 255u - (((kb >> 2) - 1u) * 16u + ((ka >> 2) - 1u));
     uint32_t boff = 0;
     if (active) {
         // window positions of each layer's first hit (layer-major lists)

@@ -13,10 +13,10 @@
 // one v_min_f64 keeps both the smallest chi2 and, among equal ones, the
 // lowest index.  Otherwise a compare-and-select keeps them (general form).
 //
-// Rows are expected sorted by (n3, n2) within a wavefront, so that the last
-// lane holds the wavefront's largest (n3, n2); every lane is active.  Within
-// a row the combinations run in (i_a, i_b) order, which is their order in
-// the combination index k because a comes before b.
+// Rows are expected sorted by (n3, n2), largest first, within a wavefront, so
+// that the first lane holds the wavefront's largest (n3, n2); every lane is
+// active.  Within a row the combinations run in (i_a, i_b) order, which is
+// their order in the combination index k because a comes before b.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
