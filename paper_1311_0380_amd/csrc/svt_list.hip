@@ -17,8 +17,10 @@
 //      (i0, i1) and a run of at most 32 / n3 values of i2, so that a piece
 //      has at most 32 combinations.  The pieces get places in road order
 //      (their combinations then come in combination order) and in a list
-//      binned by (n3, piece length), which gives the lanes of a wavefront
-//      the same trip counts; the sub-chunk's hits are staged in LDS.
+//      binned by (n3, piece length), largest first, which gives the lanes of
+//      a wavefront the same trip counts and leaves the smallest pieces to the
+//      last, partial pass over the list; the sub-chunk's hits are staged in
+//      LDS.
 //   B  one lane per piece (two pieces per thread at a time, so that their
 //      loads overlap): its combinations' constraint rows and chi2 in fp64,
 //      exact as in the fit (every value is an integer below 2^53 whenever
@@ -370,8 +372,9 @@ __global__ void __launch_bounds__(kBlock) list_kernel(ListArgs a)
             }
             uint32_t boff_full = 0, boff_last = 0;
             const uint32_t plast = n2 - (npc - 1u) * P2;   // length of the last run of i2
-            const uint32_t kfull = (n3 - 1u) * 16u + (min(P2, n2) - 1u);
-            const uint32_t klast = (n3 - 1u) * 16u + (plast - 1u);
+            // bin keys in descending (n3, run length): the largest pieces first
+            const uint32_t kfull = 255u - ((n3 - 1u) * 16u + (min(P2, n2) - 1u));
+            const uint32_t klast = 255u - ((n3 - 1u) * 16u + (plast - 1u));
             const bool split = plast != min(P2, n2);        // the last run is shorter
             if (active && pieces) {
                 // (a road with pieces has hit counts in 1..16: both keys < 256)
