@@ -679,7 +679,7 @@ def section_copy(args, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--copies", type=int, default=32)
     ap.add_argument("--passes-per-launch", type=int, default=0,

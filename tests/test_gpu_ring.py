@@ -160,7 +160,14 @@ def test_ring_rules(env):
     assert svt.svt_ring_create(ctx, [bs], [rs], 0)[0] == svt.SVT_E_INVAL
     assert svt.svt_ring_create(ctx, [bs, bs], [rs, rs], 1)[0] == svt.SVT_E_INVAL
     assert svt.svt_ring_create(ctx, [bs], [rs], 2, -1)[0] == svt.SVT_E_INVAL
-    assert svt.svt_ring_create(ctx, [bs], [rs], 2, 65)[0] == svt.SVT_E_INVAL
+    assert svt.svt_ring_create(ctx, [bs], [rs], 2, 129)[0] == svt.SVT_E_INVAL
+    # the largest count is taken, and clamped to the passes there are
+    st, r128 = svt.svt_ring_create(ctx, [bs], [rs], 2, 128)
+    svt.check(st)
+    try:
+        assert svt.svt_ring_info(r128) == (2, 2, 1)
+    finally:
+        svt.svt_ring_destroy(r128)
     st, ring = svt.svt_ring_create(ctx, [bs], [rs], 3)
     svt.check(st)
     try:
