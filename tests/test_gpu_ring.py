@@ -79,15 +79,15 @@ def ring_case(svt, ctx, oracle_lib, batches, consts, n_passes, per_launch, runs=
     svt.check(svt.svt_load_constants(ctx, consts.coef, consts.offset, consts.chi2_cut))
     dbs = [svt.to_device(b) for b in batches]
     drs = [svt.DeviceResults(b.n_events, b.n_roads) for b in batches]
-    wants, tot = [], dict(total_comb=0, total_pass=0, total_tracks=0)
+    wants, sums, tot = [], [], dict(total_comb=0, total_pass=0, total_tracks=0)
     for b in batches:
-        rc, w, _ = oracle_lib.fit_batch(b, consts, n_threads=8)
+        rc, w, s = oracle_lib.fit_batch(b, consts, n_threads=8)
         assert rc == 0
         wants.append(w)
+        sums.append(s)
     for p in range(n_passes):
-        summ = oracle_lib.fit_batch(batches[p % len(batches)], consts, n_threads=8)[2]
         for k in tot:
-            tot[k] += summ[k]
+            tot[k] += sums[p % len(batches)][k]
     st, ring = svt.svt_ring_create(ctx, [d.struct() for d in dbs], [r.struct() for r in drs],
                                    n_passes, per_launch)
     svt.check(st, "svt_ring_create")
@@ -129,6 +129,26 @@ def shape_batches(seed=91):
     out.append(synth.make_events(rng, rpe, rng.integers(1, 5, (nr, 4)), consts.n_sectors,
                                  rng.random(nr) < 0.5, consts))
     return out, consts
+
+
+@pytest.mark.parametrize("n_passes,per_launch,shape", [(128, 0, (128, 128, 1)), (130, 0, (130, 65, 2)),
+                                                       (100, 128, (100, 100, 1))])
+def test_ring_many_passes_per_launch(env, oracle_lib, n_passes, per_launch, shape):
+    """Long launches (the automatic choice takes up to 128 passes in one):
+    every batch's results and the summed totals equal the oracle's."""
+    svt, ctx = env
+    batches, consts = shape_batches(seed=93)
+    svt.check(svt.svt_load_constants(ctx, consts.coef, consts.offset, consts.chi2_cut))
+    dbs = [svt.to_device(b) for b in batches]
+    drs = [svt.DeviceResults(b.n_events, b.n_roads) for b in batches]
+    st, ring = svt.svt_ring_create(ctx, [d.struct() for d in dbs], [r.struct() for r in drs],
+                                   n_passes, per_launch)
+    svt.check(st, "svt_ring_create")
+    try:
+        assert svt.svt_ring_info(ring) == shape
+    finally:
+        svt.svt_ring_destroy(ring)
+    ring_case(svt, ctx, oracle_lib, batches, consts, n_passes, per_launch, runs=1)
 
 
 @pytest.mark.parametrize("tuning", [dict(), dict(events_per_chunk=1), dict(events_per_chunk=3, schedule=2),
