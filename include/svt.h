@@ -366,8 +366,8 @@ svt_status svt_plan_fit(svt_plan *plan, const svt_event_batch *batch, const svt_
 typedef struct svt_ring svt_ring;
 /* passes_per_launch: passes one kernel launch covers (each of its batches
  * spread over the same number of blocks), 1..128, or 0 for automatic (at
- * most 128, the passes split evenly over the launches).  Results do not depend on
- * it. */
+ * most 128, the passes split evenly over the launches).  Results do not
+ * depend on it. */
 svt_status svt_ring_create(svt_ctx *ctx, int32_t n_batches, const svt_event_batch *batches,
                            const svt_results *results, int32_t n_passes, int32_t passes_per_launch,
                            svt_ring **out);

@@ -949,11 +949,6 @@ __global__ void zero_i64(int64_t *p)
     if (threadIdx.x == 0) p[0] = 0;
 }
 
-__global__ void copy_seq(const uint32_t *src, uint32_t *dst)
-{
-    if (threadIdx.x == 0) *dst = *src;
-}
-
 }  // namespace
 
 hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, hipStream_t stream)
@@ -972,11 +967,6 @@ hipError_t launch_fit(const FitArgs &a, int grid, hipStream_t stream, hipEvent_t
     return hipGetLastError();
 }
 
-hipError_t launch_copy_seq(const uint32_t *src, uint32_t *dst, hipStream_t stream)
-{
-    hipLaunchKernelGGL(copy_seq, dim3(1), dim3(64), 0, stream, src, dst);
-    return hipGetLastError();
-}
 
 size_t comb_offsets_scratch_bytes(int32_t n_roads)
 {

@@ -85,10 +85,6 @@ hipError_t launch_fit(const FitArgs &a, int grid, hipStream_t stream, hipEvent_t
 // n_batches batches in one launch of the block kernel: args is device memory
 // holding one FitArgs per batch; batch i is spread over blocks [i per, (i+1) per).
 hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, hipStream_t stream);
-// One thread copies a request's sequence number from host-mapped memory to
-// device memory (the first node of a ring's graph; the fit kernels then read
-// it from device memory).
-hipError_t launch_copy_seq(const uint32_t *src, uint32_t *dst, hipStream_t stream);
 hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
                                int64_t *scratch, hipStream_t stream);
 size_t comb_offsets_scratch_bytes(int32_t n_roads);

@@ -1,6 +1,6 @@
 // Block partials of a ring run reduced on the device, so that the host reads
 // one summary instead of every block's (a 100-pass run over the 3000-event
-// batch has 76,800 of them).  The same sums, minima and sequence check as
+// batch has 75,000 of them).  The same sums, minima and sequence check as
 // the host's reduction of a single request's partials.
 #include "svt_partials.h"
 
@@ -61,29 +61,44 @@ __device__ void reduce_range(const BlockPartial *in, int64_t lo, int64_t hi, uin
     }
 }
 
-__global__ void __launch_bounds__(kBlock) reduce_partials_a(const BlockPartial *in, int64_t n,
-                                                            BlockPartial *mid, const uint32_t *seq_dev)
+// One launch: every block reduces its share of in[0, n) into mid[block];
+// the block that finishes last (a counter, released and acquired at device
+// scope, so that the other blocks' mid entries are visible to it) reduces
+// mid into *out, resets the counter and advances the run's sequence number.
+__global__ void __launch_bounds__(kBlock) reduce_partials(const BlockPartial *in, int64_t n,
+                                                          BlockPartial *mid, BlockPartial *out,
+                                                          uint32_t *seq_dev, uint32_t *counter)
 {
+    __shared__ uint32_t s_last;
+    const uint32_t seq = *seq_dev;
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = min(n, (int64_t)blockIdx.x * per), hi = min(n, lo + per);
-    reduce_range(in, lo, hi, *seq_dev, mid + blockIdx.x);
-}
-
-__global__ void __launch_bounds__(kBlock) reduce_partials_b(const BlockPartial *mid, int32_t n,
-                                                            BlockPartial *out, const uint32_t *seq_dev)
-{
-    reduce_range(mid, 0, n, *seq_dev, out);
+    reduce_range(in, lo, hi, seq, mid + blockIdx.x);
+    if (threadIdx.x == 0) {
+        // (thread 0 wrote mid[block]; the release orders that write first)
+        const uint32_t done =
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = done == gridDim.x - 1u ? 1u : 0u;
+    }
+    __syncthreads();
+    if (s_last == 0u) return;
+    // every thread of the last block acquires before it reads mid
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    reduce_range(mid, 0, gridDim.x, seq, out);
+    if (threadIdx.x == 0) {
+        *counter = 0u;          // ready for the next run (stream order)
+        *seq_dev = seq + 1u;    // the next run's sequence number
+    }
 }
 
 }  // namespace
 
 hipError_t launch_reduce_partials(const BlockPartial *in, int64_t n, BlockPartial *mid,
-                                  BlockPartial *out, const uint32_t *seq_dev, hipStream_t stream)
+                                  BlockPartial *out, uint32_t *seq_dev, uint32_t *counter,
+                                  hipStream_t stream)
 {
-    hipLaunchKernelGGL(reduce_partials_a, dim3(kPartialRedBlocks), dim3(kBlock), 0, stream, in, n, mid,
-                       seq_dev);
-    hipLaunchKernelGGL(reduce_partials_b, dim3(1), dim3(kBlock), 0, stream, mid,
-                       (int32_t)kPartialRedBlocks, out, seq_dev);
+    hipLaunchKernelGGL(reduce_partials, dim3(kPartialRedBlocks), dim3(kBlock), 0, stream, in, n, mid,
+                       out, seq_dev, counter);
     return hipGetLastError();
 }
 

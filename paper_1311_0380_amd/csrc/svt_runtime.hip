@@ -43,6 +43,7 @@ svt_status hip_fail(hipError_t e, const char *what)
     } while (0)
 
 constexpr int kSlots = 64;
+constexpr int kRingCounter = 32;   // a ring's reduction counter: seq_dev[32], 128 bytes on
 
 // Scratch of svt_list_passing_noalloc: the running sums of the pass counts
 // (one int64 per tile of svt::kListTile roads, plus the total) for at most
@@ -85,6 +86,7 @@ struct Slot {
     int grid = 0;                            // blocks of the request in flight
     svt_plan *plan = nullptr;                // plan of the request, if any
     svt_ring *ring = nullptr;                // ring of the request, if any
+    uint32_t ring_seq = 0;                   // a ring run's sequence number
     DevBuf stage;                            // device staging for host inputs / results
     DevBuf scan;                             // scratch of the running sums (offsets scans)
     svt_status host_status = SVT_OK;
@@ -152,10 +154,13 @@ struct svt_ring {
     int32_t per_launch = 1;                 // passes per kernel launch
     int total_parts = 0;                    // block partials of all passes
     svt::BlockPartial *parts_dev = nullptr; // device [total_parts], pass after pass
-    svt::BlockPartial *mid_dev = nullptr;   // device: the first reduction pass's partials
+    svt::BlockPartial *mid_dev = nullptr;   // device: the reduction blocks' partials
     svt::BlockPartial *summary = nullptr;   // host-mapped: the run's reduced partial
-    uint32_t *seq_host = nullptr;           // host-mapped: the run's ticket
-    uint32_t *seq_dev = nullptr;            // device copy the fit kernels read
+    // device: [0] the run's sequence number, which the fit kernels read and
+    // the reduction advances at the end of each run; [kRingCounter] the
+    // reduction's block counter
+    uint32_t *seq_dev = nullptr;
+    uint32_t runs = 0;                      // runs enqueued (the next run's sequence number)
     svt::FitArgs *args_dev = nullptr;       // device: the launch arguments of every pass
     size_t args_bytes = 0;
     uint64_t const_gen = 0;
@@ -959,7 +964,7 @@ svt_status svt_result(svt_ctx *c, svt_ticket t, int32_t wait_us, svt_summary *ou
     bool complete = true;
     for (int b = 0; b < s.grid; ++b) {
         const svt::BlockPartial p = s.parts[b];
-        complete = complete && p.seq == (uint32_t)t;
+        complete = complete && p.seq == (s.ring ? s.ring_seq : (uint32_t)t);
         comb += p.comb;
         pass += p.pass;
         trk += p.tracks;
@@ -1353,7 +1358,6 @@ static void ring_free(svt_ring *r)
     if (r->args_dev) dev_free(r->ctx, r->args_dev, r->args_bytes);
     if (r->parts_dev) dev_free(r->ctx, r->parts_dev, sizeof(svt::BlockPartial) * r->total_parts);
     if (r->mid_dev) dev_free(r->ctx, r->mid_dev, sizeof(svt::BlockPartial) * svt::kPartialRedBlocks);
-    if (r->seq_host) (void)hipHostFree(r->seq_host);
     if (r->summary) (void)hipHostFree(r->summary);
     delete r;
 }
@@ -1414,10 +1418,16 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         part_off[p + 1] = part_off[p] + (k > 1 ? launch_per[p / k] : shapes[p % n_batches].grid);
     r->total_parts = part_off[n_passes];
     // the blocks' partials stay in device memory and are reduced there (by
-    // the last two nodes of the graph) into one host-mapped summary
+    // the last node of the graph) into one host-mapped summary
     svt_status st = dev_alloc(c, reinterpret_cast<void **>(&r->seq_dev), 256);
     if (st != SVT_OK) {
         delete r;
+        return st;
+    }
+    // (before any capture: the first run's sequence number and the counter)
+    if (hipMemset(r->seq_dev, 0, 256) != hipSuccess) {
+        st = hip_fail(hipGetLastError(), "hipMemset");
+        ring_free(r);
         return st;
     }
     st = dev_alloc(c, reinterpret_cast<void **>(&r->parts_dev),
@@ -1430,20 +1440,16 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         return st;
     }
     if (hipHostMalloc(reinterpret_cast<void **>(&r->summary), sizeof(svt::BlockPartial),
-                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void **>(&r->seq_host), 64,
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         st = hip_fail(hipGetLastError(), "hipHostMalloc");
         ring_free(r);
         return st;
     }
     memset(r->summary, 0, sizeof(svt::BlockPartial));
-    *r->seq_host = 0;
+    r->summary->seq = 0xFFFFFFFFu;   // no run's number until a run writes it
     svt::BlockPartial *parts_dev = r->parts_dev;
     svt::BlockPartial *summary_dev = static_cast<svt::BlockPartial *>(
         const_cast<void *>(device_view(r->summary, SVT_MEM_MAPPED)));
-    const uint32_t *seq_src =
-        static_cast<const uint32_t *>(device_view(r->seq_host, SVT_MEM_MAPPED));
 
     // the launch arguments of every pass
     std::vector<svt::FitArgs> args(n_passes);
@@ -1489,13 +1495,13 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         }
     }
 
-    // the graph: the run's ticket into device memory, the launches in order,
-    // then the reduction of their partials
+    // the graph: the launches in order, then the reduction of their partials
+    // (which also advances the sequence number the next run's blocks read)
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e2 = svt::launch_copy_seq(seq_src, r->seq_dev, cs);
+        hipError_t e2 = hipSuccess;
         for (int l = 0; l < n_launch && e2 == hipSuccess; ++l) {
             const int p0 = l * k, np = (p0 + k <= n_passes) ? k : n_passes - p0;
             if (k > 1)
@@ -1505,7 +1511,7 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         }
         if (e2 == hipSuccess)
             e2 = svt::launch_reduce_partials(parts_dev, r->total_parts, r->mid_dev, summary_dev,
-                                             r->seq_dev, cs);
+                                             r->seq_dev, r->seq_dev + kRingCounter, cs);
         e = hipStreamEndCapture(cs, &r->graph);
         if (e == hipSuccess && e2 != hipSuccess) e = e2;
     }
@@ -1534,13 +1540,13 @@ svt_status svt_ring_run(svt_ring *r, void *hip_stream, svt_ticket *ticket)
     if (s.busy) return SVT_E_AGAIN;
     DeviceGuard g(c->device);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);  // NULL: the null stream
-    // no run of this ring is in flight, so its kernels are not reading the
-    // word while it changes
-    *r->seq_host = (uint32_t)c->next_ticket;
     auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); }, [] {});
     guard.enqueuing();
     HIP_TRY(hipEventRecord(s.ev_start, st));
     HIP_TRY(hipGraphLaunch(r->exec, st));
+    // the graph advances the device's sequence number once it has run, so
+    // the host's count follows every launch that was enqueued
+    const uint32_t run_seq = r->runs++;
     HIP_TRY(hipEventRecord(s.ev_end, st));
     guard.submitted();
     s.timed = true;
@@ -1548,6 +1554,7 @@ svt_status svt_ring_run(svt_ring *r, void *hip_stream, svt_ticket *ticket)
     s.ticket = c->next_ticket++;
     s.parts = r->summary;   // the graph reduced the blocks' partials into it
     s.grid = 1;
+    s.ring_seq = run_seq;
     s.plan = nullptr;
     s.ring = r;
     r->busy = true;
