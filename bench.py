@@ -8,7 +8,9 @@ Headline step = one pass of the fit over the scaled-up plain-fit workload
 half the roads with a planted track: 192,000 roads, ~7.5 M combinations),
 inputs and results resident in HBM.  The K timed passes run back to back as
 captured graph launches of up to 100 passes (rings), and rotate over 32
-input copies so that they read HBM rather than the 256 MB last-level cache.
+input copies so that they read HBM rather than the 256 MB last-level cache;
+at least 2000 untimed passes of the same rings come first, whatever --warmup
+asks for, so that the clocks have settled.
 The per-request form (one svt_fit_events call per pass) is reported beside
 it.  Further sections: the paper's sweep (1-3000 events x 2048 combinations,
 with the oracle on one and on all host threads), the list of every passing
@@ -45,6 +47,11 @@ def algorithmic_bytes(n_events, n_roads, n_hits, n_sectors=72):
     inputs = 4 * (n_events + 1) + n_roads * (1 + 4 + 4 + 4) + 4 + 2 * n_hits
     outputs = n_roads * (4 + 4 + 4 + 8 + 12 + 4) + 4 * n_events
     return inputs + outputs + n_sectors * 42 * 4
+
+
+# untimed passes before the timed region, whatever --warmup asks for (about
+# 17 ms of fit work: the chip's clocks settle within some 20 ms of it)
+WARM_PASSES = 2000
 
 
 def kernel_source_hash():
@@ -205,9 +212,12 @@ def section_fit(args, svt, synth, torch):
     shapes = [svt.svt_ring_info(r) for r, _ in timed]
     per_launch = shapes[0][1]
     launches = sum(x[2] for x in shapes)
-    # warm-up: the timed rings themselves, at least --warmup passes (the chip
-    # takes some 20 ms of this work to reach its steady clocks)
-    run_rings(svt, ctx.handle, timed, stream, repeat=max(1, -(-args.warmup // args.steps)))
+    # warm-up: the timed rings themselves, at least --warmup passes and never
+    # fewer than WARM_PASSES (the chip takes some 20 ms of this work to reach
+    # its steady clocks; a short --warmup would otherwise time the ramp)
+    warm = max(args.warmup, WARM_PASSES)
+    warm_repeat = max(1, -(-warm // args.steps))
+    run_rings(svt, ctx.handle, timed, stream, repeat=warm_repeat)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total, dev = run_rings(svt, ctx.handle, timed, stream)
@@ -236,7 +246,8 @@ def section_fit(args, svt, synth, torch):
                 "combinations": int(total // passes), "chi2_cut": consts.chi2_cut,
                 "device": info["arch"], "compute_units": info["compute_units"],
                 "tuning": ctx.tuning(), "input_copies": args.copies, "ring_passes": per_ring,
-                "passes_per_launch": per_launch},
+                "passes_per_launch": per_launch,
+                "warmup_passes_run": warm_repeat * args.steps},
         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": achieved / HBM_PEAK_GBS,
                   "traffic": None if traffic is None else traffic * passes // launches,
