@@ -219,6 +219,11 @@ def section_fit(args, svt, synth, torch):
     warm_repeat = max(1, -(-warm // args.steps))
     run_rings(svt, ctx.handle, timed, stream, repeat=warm_repeat)
     torch.cuda.synchronize()
+    # and one untimed region shaped as the timed one (from a synchronized
+    # start): the first such region after the long warm-up ran slower on the
+    # host side (a 20-pass region: 10.3-13.0 us per pass, then 9.7-9.8)
+    run_rings(svt, ctx.handle, timed, stream)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     total, dev = run_rings(svt, ctx.handle, timed, stream)
     torch.cuda.synchronize()
@@ -247,7 +252,7 @@ def section_fit(args, svt, synth, torch):
                 "device": info["arch"], "compute_units": info["compute_units"],
                 "tuning": ctx.tuning(), "input_copies": args.copies, "ring_passes": per_ring,
                 "passes_per_launch": per_launch,
-                "warmup_passes_run": warm_repeat * args.steps},
+                "warmup_passes_run": (warm_repeat + 1) * args.steps},
         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": achieved / HBM_PEAK_GBS,
                   "traffic": None if traffic is None else traffic * passes // launches,

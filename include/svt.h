@@ -352,8 +352,11 @@ svt_status svt_plan_fit(svt_plan *plan, const svt_event_batch *batch, const svt_
  * A read-out that fills a ring of device buffers while the GPU fits them in
  * order is the steady state of the fit; the paper times 100 repetitions of
  * each sample back to back (Sec. 4.1), which a ring of 100 passes gives
- * without host launch gaps between them.  svt_ring_create captures one graph
- * of n_passes fit kernels: pass p fits batches[p % n_batches] into
+ * without host launch gaps between them.  svt_ring_create prepares the
+ * launches of n_passes fit passes and the reduction of their block sums,
+ * captured as one graph when there are more than four launches, and
+ * enqueued one by one at each run otherwise (a graph launch adds some 20 us
+ * from the host call to its first kernel): pass p fits batches[p % n_batches] into
  * results[p % n_batches] (a later pass over the same batch rewrites the same
  * results).  Every batch and results must be device memory (SVT_MEM_DEVICE),
  * without comb_offsets, and follows the svt_fit_events layout; the arrays
@@ -371,7 +374,7 @@ typedef struct svt_ring svt_ring;
 svt_status svt_ring_create(svt_ctx *ctx, int32_t n_batches, const svt_event_batch *batches,
                            const svt_results *results, int32_t n_passes, int32_t passes_per_launch,
                            svt_ring **out);
-/* Replay the ring's graph on hip_stream (asynchronous; one run per ring in
+/* Run the ring's passes on hip_stream (asynchronous; one run per ring in
  * flight, else SVT_E_AGAIN).  svt_result on the ring's context then gives the
  * sums over all passes (total_comb = sum over passes of each pass's
  * combinations, and so on), the lowest err_road / err_event any pass

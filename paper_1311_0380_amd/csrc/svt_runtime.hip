@@ -43,6 +43,13 @@ svt_status hip_fail(hipError_t e, const char *what)
     } while (0)
 
 constexpr int kSlots = 64;
+// Rings of at most this many fit launches enqueue their kernels on the
+// caller's stream at each run instead of launching a captured graph: a graph
+// launch took some 20 us longer from the host call to its first kernel.
+#ifndef SVT_RING_DIRECT_MAX
+#define SVT_RING_DIRECT_MAX 4
+#endif
+constexpr int kRingDirectMax = SVT_RING_DIRECT_MAX;
 constexpr int kRingCounter = 32;   // a ring's reduction counter: seq_dev[32], 128 bytes on
 
 // Scratch of svt_list_passing_noalloc: the running sums of the pass counts
@@ -166,6 +173,16 @@ struct svt_ring {
     uint64_t const_gen = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // a ring of few launches enqueues its kernels itself (no graph): the
+    // first pass of each launch, its passes and its grid; the passes'
+    // arguments on the host for one-pass launches
+    struct Launch {
+        int32_t p0, np, grid;
+    };
+    std::vector<Launch> launches;
+    std::vector<svt::FitArgs> args_host;
+    svt::BlockPartial *summary_dev = nullptr;
+    bool direct = false;
     bool busy = false;
 };
 
@@ -1495,6 +1512,17 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         }
     }
 
+    r->summary_dev = summary_dev;
+    for (int l = 0; l < n_launch; ++l) {
+        const int p0 = l * k, np = (p0 + k <= n_passes) ? k : n_passes - p0;
+        r->launches.push_back({p0, np, k > 1 ? launch_per[l] : shapes[p0 % n_batches].grid});
+    }
+    if (n_launch <= kRingDirectMax) {
+        r->direct = true;
+        if (k == 1) r->args_host = args;
+        *out = r;
+        return SVT_OK;
+    }
     // the graph: the launches in order, then the reduction of their partials
     // (which also advances the sequence number the next run's blocks read)
     hipStream_t cs = nullptr;
@@ -1543,9 +1571,21 @@ svt_status svt_ring_run(svt_ring *r, void *hip_stream, svt_ticket *ticket)
     auto guard = svt::make_submit_guard([st] { (void)hipStreamSynchronize(st); }, [] {});
     guard.enqueuing();
     HIP_TRY(hipEventRecord(s.ev_start, st));
-    HIP_TRY(hipGraphLaunch(r->exec, st));
-    // the graph advances the device's sequence number once it has run, so
-    // the host's count follows every launch that was enqueued
+    if (r->direct) {
+        // the same kernels, in the same order, as a captured ring's graph
+        for (const svt_ring::Launch &l : r->launches) {
+            if (r->per_launch > 1)
+                HIP_TRY(svt::launch_fit_multi(r->args_dev + l.p0, l.np, l.grid, st));
+            else
+                HIP_TRY(svt::launch_fit(r->args_host[l.p0], l.grid, st));
+        }
+        HIP_TRY(svt::launch_reduce_partials(r->parts_dev, r->total_parts, r->mid_dev, r->summary_dev,
+                                            r->seq_dev, r->seq_dev + kRingCounter, st));
+    } else {
+        HIP_TRY(hipGraphLaunch(r->exec, st));
+    }
+    // the run's last kernel advances the device's sequence number, so the
+    // host's count follows every run that was enqueued
     const uint32_t run_seq = r->runs++;
     HIP_TRY(hipEventRecord(s.ev_end, st));
     guard.submitted();

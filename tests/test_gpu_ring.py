@@ -151,6 +151,17 @@ def test_ring_many_passes_per_launch(env, oracle_lib, n_passes, per_launch, shap
     ring_case(svt, ctx, oracle_lib, batches, consts, n_passes, per_launch, runs=1)
 
 
+@pytest.mark.parametrize("n_passes,per_launch", [(3, 1), (4, 1), (5, 1), (9, 2), (8, 2)])
+def test_ring_direct_and_graph_runs(env, oracle_lib, n_passes, per_launch):
+    """Rings of up to four launches enqueue their kernels at each run, longer
+    ones replay a captured graph: both sides of that boundary, with one-pass
+    and two-pass launches, give the oracle's results and totals, run after
+    run (the sequence number advances the same way in both forms)."""
+    svt, ctx = env
+    batches, consts = shape_batches(seed=95)
+    ring_case(svt, ctx, oracle_lib, batches, consts, n_passes, per_launch, runs=3)
+
+
 @pytest.mark.parametrize("tuning", [dict(), dict(events_per_chunk=1), dict(events_per_chunk=3, schedule=2),
                                     dict(blocks_per_cu=1), dict(events_per_chunk=256)])
 @pytest.mark.parametrize("per_launch", [3, 0])
