@@ -52,6 +52,8 @@ def algorithmic_bytes(n_events, n_roads, n_hits, n_sectors=72):
 # untimed passes before the timed region, whatever --warmup asks for (about
 # 17 ms of fit work: the chip's clocks settle within some 20 ms of it)
 WARM_PASSES = 2000
+# untimed regions shaped as the timed one, run just before it
+PRE_REGIONS = 3
 
 
 def kernel_source_hash():
@@ -219,11 +221,13 @@ def section_fit(args, svt, synth, torch):
     warm_repeat = max(1, -(-warm // args.steps))
     run_rings(svt, ctx.handle, timed, stream, repeat=warm_repeat)
     torch.cuda.synchronize()
-    # and one untimed region shaped as the timed one (from a synchronized
-    # start): the first such region after the long warm-up ran slower on the
-    # host side (a 20-pass region: 10.3-13.0 us per pass, then 9.7-9.8)
-    run_rings(svt, ctx.handle, timed, stream)
-    torch.cuda.synchronize()
+    # and three untimed regions shaped as the timed one (each from a
+    # synchronized start): the first two such regions after the long warm-up
+    # ran slower on the host side (20-pass regions, wall time per pass:
+    # 12.7, 11.6, then 9.7-9.8 us, at the same device time)
+    for _ in range(PRE_REGIONS):
+        run_rings(svt, ctx.handle, timed, stream)
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     total, dev = run_rings(svt, ctx.handle, timed, stream)
     torch.cuda.synchronize()
@@ -252,7 +256,7 @@ def section_fit(args, svt, synth, torch):
                 "device": info["arch"], "compute_units": info["compute_units"],
                 "tuning": ctx.tuning(), "input_copies": args.copies, "ring_passes": per_ring,
                 "passes_per_launch": per_launch,
-                "warmup_passes_run": (warm_repeat + 1) * args.steps},
+                "warmup_passes_run": (warm_repeat + PRE_REGIONS) * args.steps},
         roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": achieved / HBM_PEAK_GBS,
                   "traffic": None if traffic is None else traffic * passes // launches,

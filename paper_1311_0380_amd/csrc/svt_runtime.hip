@@ -335,16 +335,16 @@ struct LaunchShape {
 };
 
 LaunchShape launch_shape(const svt_ctx *c, const svt_tuning &t, int32_t ne, int32_t nr, int32_t nh,
-                         bool persistent)
+                         bool persistent, int chunk_mult = 1)
 {
     LaunchShape ls;
     const int bpc = t.blocks_per_cu > 0 ? t.blocks_per_cu : 5;
     const int sizing = t.blocks_per_cu > 0 ? t.blocks_per_cu : 3;
     ls.epc = t.events_per_chunk > 0
                  ? t.events_per_chunk
-                 : auto_events_per_chunk(ne, nr,
-                                         block_roads_per_chunk(nr, nh, (int64_t)c->cu_count * sizing),
-                                         svt::kMaxEventsPerChunk);
+                 : auto_events_per_chunk(
+                       ne, nr, block_roads_per_chunk(nr, nh, (int64_t)c->cu_count * sizing) * chunk_mult,
+                       svt::kMaxEventsPerChunk);
     int64_t grid = (int64_t)c->cu_count * bpc;
     if (!persistent && t.schedule == 3) {
         // balanced by roads: at least 64 roads per block
@@ -1417,10 +1417,23 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     if (k < 1) k = 1;
     if (k > n_passes) k = n_passes;
     r->per_launch = k;
+    // chunks of a multi-pass launch: three times a lone pass's (three full
+    // sub-chunks of 256 roads per block on the 3000 x 64-road batch) when the
+    // launch still has at least two blocks per grid slot, since the blocks of
+    // its other passes fill the grid; each block's start-up is then shared by
+    // three sub-chunks (back to back: 8.30 us per pass with 4 events per
+    // chunk, 7.84 with 8, 7.73 with 12 or 16, 7.81 with 32, 8.59 with 6,
+    // whose 384 roads leave a half-empty sub-chunk; a 20-pass launch: 8.87
+    // against 8.68 us per pass with 12)
     std::vector<LaunchShape> shapes(n_batches);
-    for (int i = 0; i < n_batches; ++i)
-        shapes[i] = launch_shape(c, c->tuning, batches[i].n_events, batches[i].n_roads,
-                                 batches[i].n_hits, false);
+    const int64_t slots = (int64_t)c->cu_count * 5;
+    for (int i = 0; i < n_batches; ++i) {
+        const svt_event_batch &b = batches[i];
+        shapes[i] = launch_shape(c, c->tuning, b.n_events, b.n_roads, b.n_hits, false);
+        const int64_t chunks = b.n_events > 0 ? ((int64_t)b.n_events + shapes[i].epc - 1) / shapes[i].epc : 0;
+        if (k > 1 && (int64_t)k * chunks >= 2 * 3 * slots)
+            shapes[i] = launch_shape(c, c->tuning, b.n_events, b.n_roads, b.n_hits, false, 3);
+    }
     // each launch of the block kernel gives every batch the same number of
     // blocks (the largest grid of its passes); block partials pass by pass
     const int n_launch = (n_passes + k - 1) / k;
