@@ -875,16 +875,30 @@ fit_kernel(FitArgs a)
     fit_block(*(const FitArgs *)pa, (int32_t)blockIdx.x, (int32_t)gridDim.x);
 }
 
-// Several batches in one launch: batch i takes blocks [i per, (i + 1) per),
-// so that blocks of later batches start wherever blocks of earlier ones end.
+// Several batches in one launch, so that blocks of later batches start
+// wherever blocks of earlier ones end: batch i < n1 takes blocks
+// [i per, (i + 1) per); the batches after them take per2 blocks each (the
+// launch's last batches, which can be cut into smaller chunks than the
+// others, so that the launch's last blocks are short ones).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5)))
-fit_kernel_multi(const FitArgs *__restrict__ args, int32_t per)
+fit_kernel_multi(const FitArgs *__restrict__ args, int32_t per, int32_t n1, int32_t per2)
 {
-    const int32_t i = (int32_t)blockIdx.x / per;
+    const int32_t b = (int32_t)blockIdx.x, head = n1 * per;
+    int32_t i, lb, nb;
+    if (b < head) {
+        i = b / per;
+        lb = b - i * per;
+        nb = per;
+    } else {
+        const int32_t t = (b - head) / per2;
+        i = n1 + t;
+        lb = b - head - t * per2;
+        nb = per2;
+    }
     // read through the constant address space: the argument loads can then be
     // repeated where they are used instead of holding every field in registers
     ConstArgs *ca = (ConstArgs *)args;
-    fit_block(*(const FitArgs *)&ca[i], (int32_t)blockIdx.x - i * per, per);
+    fit_block(*(const FitArgs *)&ca[i], lb, nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -951,10 +965,10 @@ __global__ void zero_i64(int64_t *p)
 
 }  // namespace
 
-hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, hipStream_t stream)
+hipError_t launch_fit_multi(const FitArgs *args, int n1, int per, int n2, int per2, hipStream_t stream)
 {
-    hipLaunchKernelGGL(fit_kernel_multi, dim3(n_batches * per), dim3(kBlock), 0, stream, args,
-                       (int32_t)per);
+    hipLaunchKernelGGL(fit_kernel_multi, dim3(n1 * per + n2 * per2), dim3(kBlock), 0, stream, args,
+                       (int32_t)per, (int32_t)n1, (int32_t)(per2 > 0 ? per2 : 1));
     return hipGetLastError();
 }
 

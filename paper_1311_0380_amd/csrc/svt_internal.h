@@ -82,9 +82,11 @@ struct FitArgs {
 // (no separate event packets on the stream).
 hipError_t launch_fit(const FitArgs &a, int grid, hipStream_t stream, hipEvent_t start = nullptr,
                       hipEvent_t stop = nullptr);
-// n_batches batches in one launch of the block kernel: args is device memory
-// holding one FitArgs per batch; batch i is spread over blocks [i per, (i+1) per).
-hipError_t launch_fit_multi(const FitArgs *args, int n_batches, int per, hipStream_t stream);
+// n1 + n2 batches in one launch of the block kernel: args is device memory
+// holding one FitArgs per batch; batch i < n1 is spread over blocks
+// [i per, (i+1) per), and batch n1 + j over the per2 blocks after the first
+// n1 per and j per2.
+hipError_t launch_fit_multi(const FitArgs *args, int n1, int per, int n2, int per2, hipStream_t stream);
 hipError_t launch_comb_offsets(const int32_t *ncomb, int64_t *comb_offsets, int32_t n_roads,
                                int64_t *scratch, hipStream_t stream);
 size_t comb_offsets_scratch_bytes(int32_t n_roads);

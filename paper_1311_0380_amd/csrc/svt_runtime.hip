@@ -177,7 +177,8 @@ struct svt_ring {
     // first pass of each launch, its passes and its grid; the passes'
     // arguments on the host for one-pass launches
     struct Launch {
-        int32_t p0, np, grid;
+        int32_t p0, np, grid;        // first pass, head passes, blocks per head pass
+        int32_t n_tail, tail_grid;   // then n_tail passes of tail_grid blocks each
     };
     std::vector<Launch> launches;
     std::vector<svt::FitArgs> args_host;
@@ -1425,27 +1426,48 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     // chunk, 7.84 with 8, 7.73 with 12 or 16, 7.81 with 32, 8.59 with 6,
     // whose 384 roads leave a half-empty sub-chunk; a 20-pass launch: 8.87
     // against 8.68 us per pass with 12)
-    std::vector<LaunchShape> shapes(n_batches);
+    std::vector<LaunchShape> small(n_batches), shapes(n_batches);
     const int64_t slots = (int64_t)c->cu_count * 5;
     for (int i = 0; i < n_batches; ++i) {
         const svt_event_batch &b = batches[i];
-        shapes[i] = launch_shape(c, c->tuning, b.n_events, b.n_roads, b.n_hits, false);
-        const int64_t chunks = b.n_events > 0 ? ((int64_t)b.n_events + shapes[i].epc - 1) / shapes[i].epc : 0;
+        small[i] = shapes[i] = launch_shape(c, c->tuning, b.n_events, b.n_roads, b.n_hits, false);
+        const int64_t chunks = b.n_events > 0 ? ((int64_t)b.n_events + small[i].epc - 1) / small[i].epc : 0;
         if (k > 1 && (int64_t)k * chunks >= 2 * 3 * slots)
             shapes[i] = launch_shape(c, c->tuning, b.n_events, b.n_roads, b.n_hits, false, 3);
     }
-    // each launch of the block kernel gives every batch the same number of
-    // blocks (the largest grid of its passes); block partials pass by pass
+    // A launch's last blocks run on an emptying grid, so when its chunks
+    // are the larger ones its last passes keep the lone pass's chunks
+    // (shorter blocks): as many passes as fill the grid's slots once, at
+    // most a quarter of the launch's passes.  Each launch of the block
+    // kernel gives every batch of its head the same number of blocks (the
+    // largest grid of those passes) and every batch of its tail the tail's
+    // largest grid; block partials pass by pass.
+    bool larger = false;
+    for (int i = 0; i < n_batches; ++i) larger = larger || small[i].epc != shapes[i].epc;
     const int n_launch = (n_passes + k - 1) / k;
-    std::vector<int> launch_per(n_launch, 1), part_off(n_passes + 1, 0);
+    std::vector<int> launch_per(n_launch, 1), tail_per(n_launch, 1), n_tail(n_launch, 0),
+        part_off(n_passes + 1, 0);
+    std::vector<char> in_tail(n_passes, 0);
     for (int l = 0; l < n_launch; ++l) {
-        for (int p = l * k; p < n_passes && p < (l + 1) * k; ++p) {
-            const int gp = shapes[p % n_batches].grid;
-            launch_per[l] = gp > launch_per[l] ? gp : launch_per[l];
+        const int p0 = l * k, np = (p0 + k <= n_passes) ? k : n_passes - p0;
+        int m = 0;
+        int64_t cover = 0;
+        while (larger && m < np / 4 && cover < slots) {
+            cover += small[(p0 + np - 1 - m) % n_batches].grid;
+            ++m;
+        }
+        n_tail[l] = m;
+        for (int p = p0; p < p0 + np; ++p) {
+            const bool t = p >= p0 + np - m;
+            in_tail[p] = t ? 1 : 0;
+            const int gp = t ? small[p % n_batches].grid : shapes[p % n_batches].grid;
+            int &per = t ? tail_per[l] : launch_per[l];
+            per = gp > per ? gp : per;
         }
     }
     for (int p = 0; p < n_passes; ++p)
-        part_off[p + 1] = part_off[p] + (k > 1 ? launch_per[p / k] : shapes[p % n_batches].grid);
+        part_off[p + 1] = part_off[p] + (k > 1 ? (in_tail[p] ? tail_per[p / k] : launch_per[p / k])
+                                               : shapes[p % n_batches].grid);
     r->total_parts = part_off[n_passes];
     // the blocks' partials stay in device memory and are reduced there (by
     // the last node of the graph) into one host-mapped summary
@@ -1511,7 +1533,7 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         a.schedule = c->tuning.schedule;
         a.partials = parts_dev + part_off[p];
         a.seq_dev = r->seq_dev;
-        set_shape_args(c, a, shapes[p % n_batches]);
+        set_shape_args(c, a, in_tail[p] ? small[p % n_batches] : shapes[p % n_batches]);
     }
     if (k > 1) {
         r->args_bytes = sizeof(svt::FitArgs) * (size_t)n_passes;
@@ -1528,7 +1550,8 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
     r->summary_dev = summary_dev;
     for (int l = 0; l < n_launch; ++l) {
         const int p0 = l * k, np = (p0 + k <= n_passes) ? k : n_passes - p0;
-        r->launches.push_back({p0, np, k > 1 ? launch_per[l] : shapes[p0 % n_batches].grid});
+        r->launches.push_back({p0, np - n_tail[l], k > 1 ? launch_per[l] : shapes[p0 % n_batches].grid,
+                               n_tail[l], tail_per[l]});
     }
     if (n_launch <= kRingDirectMax) {
         r->direct = true;
@@ -1546,7 +1569,8 @@ svt_status svt_ring_create(svt_ctx *c, int32_t n_batches, const svt_event_batch 
         for (int l = 0; l < n_launch && e2 == hipSuccess; ++l) {
             const int p0 = l * k, np = (p0 + k <= n_passes) ? k : n_passes - p0;
             if (k > 1)
-                e2 = svt::launch_fit_multi(r->args_dev + p0, np, launch_per[l], cs);
+                e2 = svt::launch_fit_multi(r->args_dev + p0, np - n_tail[l], launch_per[l], n_tail[l],
+                                           tail_per[l], cs);
             else
                 e2 = launch_shaped(c, args[p0], shapes[p0 % n_batches], cs);
         }
@@ -1588,7 +1612,7 @@ svt_status svt_ring_run(svt_ring *r, void *hip_stream, svt_ticket *ticket)
         // the same kernels, in the same order, as a captured ring's graph
         for (const svt_ring::Launch &l : r->launches) {
             if (r->per_launch > 1)
-                HIP_TRY(svt::launch_fit_multi(r->args_dev + l.p0, l.np, l.grid, st));
+                HIP_TRY(svt::launch_fit_multi(r->args_dev + l.p0, l.np, l.grid, l.n_tail, l.tail_grid, st));
             else
                 HIP_TRY(svt::launch_fit(r->args_host[l.p0], l.grid, st));
         }

@@ -162,6 +162,22 @@ def test_ring_direct_and_graph_runs(env, oracle_lib, n_passes, per_launch):
     ring_case(svt, ctx, oracle_lib, batches, consts, n_passes, per_launch, runs=3)
 
 
+@pytest.mark.parametrize("n_passes", [20, 12])
+def test_ring_full_batch_head_and_tail_chunks(env, oracle_lib, n_passes):
+    """The 3000-event x 64-road batch and a 1000-event slice of it in one
+    ring: a multi-pass launch cuts the full batch's passes into chunks of
+    three times a lone pass's (the slice keeps the lone pass's) and its last
+    passes (enough to fill the grid once, at most a quarter of the launch:
+    four of 20, three of 12) into the lone pass's chunks, so one launch holds
+    blocks of both sizes and both kinds of batch in its head and its tail.
+    Every result equals the oracle's, run after run."""
+    svt, ctx = env
+    full, consts = synth.cfg2()
+    batches = [full, full.select_events(1000, 2000)]
+    print(f"full batch ring: {n_passes} passes", flush=True)
+    ring_case(svt, ctx, oracle_lib, batches, consts, n_passes, 0, runs=2)
+
+
 @pytest.mark.parametrize("tuning", [dict(), dict(events_per_chunk=1), dict(events_per_chunk=3, schedule=2),
                                     dict(blocks_per_cu=1), dict(events_per_chunk=256)])
 @pytest.mark.parametrize("per_launch", [3, 0])
