@@ -7,7 +7,8 @@ Headline step = one pass of the fit over the scaled-up plain-fit workload
 (3000 events x 64 roads, 1-4 hits per layer, 72 sectors, lattice constants,
 half the roads with a planted track: 192,000 roads, ~7.5 M combinations),
 inputs and results resident in HBM.  The K timed passes run back to back as
-captured graph launches of up to 100 passes (rings), and rotate over 32
+ring runs of up to 100 passes (one multi-pass fit launch and one reduction
+kernel each, enqueued on the stream), and rotate over 32
 input copies so that they read HBM rather than the 256 MB last-level cache;
 at least 2000 untimed passes of the same rings come first, whatever --warmup
 asks for, so that the clocks have settled.
@@ -195,8 +196,8 @@ def run_rings(svt, ctx, rings, stream, repeat=1):
 
 def section_fit(args, svt, synth, torch):
     """Headline: passes of the fit over the 3000-event batch, back to back.
-    The timed region runs exactly --steps passes as graph launches of at
-    most --ring-passes passes each over --copies rotating input copies (the
+    The timed region runs exactly --steps passes as ring runs of at most
+    --ring-passes passes each over --copies rotating input copies (the
     paper's repeated passes over one sample, Sec. 4.1, in steady state).
     The per-request form (one svt_fit_events per pass, over two streams)
     is measured beside it."""
@@ -249,8 +250,11 @@ def section_fit(args, svt, synth, torch):
         config={"workload": "scaled-up plain fit: 3000 events x 64 roads, 1-4 hits per layer, "
                             "72 sectors, lattice constants, half the roads with a planted track",
                 "step": "one pass of the fit over the batch; the timed passes run back to back "
-                        f"as graph launches of up to {per_ring} passes over {args.copies} "
+                        f"as ring runs of up to {per_ring} passes over {args.copies} "
                         f"rotating input copies, {per_launch} passes per kernel launch",
+                "chunks": "12 events per chunk (three 256-road sub-chunks per block) in a "
+                          "launch's passes, 4 in its last passes (enough to fill the grid once, "
+                          "at most a quarter of them)",
                 "n_events": batch.n_events, "n_roads": batch.n_roads, "n_hits": batch.n_hits,
                 "combinations": int(total // passes), "chi2_cut": consts.chi2_cut,
                 "device": info["arch"], "compute_units": info["compute_units"],
@@ -263,10 +267,10 @@ def section_fit(args, svt, synth, torch):
                   "kernel_us": launch_s * 1e6, "kernel_us_per_pass": kernel_s * 1e6,
                   "algorithmic_bytes": alg * passes // launches, "algorithmic_bytes_per_pass": alg,
                   "passes_per_launch": per_launch, "timed_launches": launches,
-                  "kernel_us_basis": "device time of the timed graph launches (events around each "
-                                     "graph launch on its stream) / kernel launches: back-to-back "
+                  "kernel_us_basis": "device time of the timed ring runs (events around each "
+                                     "run on its stream) / kernel launches: back-to-back "
                                      "fit kernels on one stream, the gaps between them and the "
-                                     "two small kernels that reduce each graph's block partials "
+                                     "small kernel that reduces each run's block partials "
                                      "included"},
         requests=requests, batch=batch, consts=consts)
     ctx.close()
@@ -705,7 +709,7 @@ def main():
     ap.add_argument("--passes-per-launch", type=int, default=0,
                     help="fit passes per kernel launch in the rings (0: the library's choice)")
     ap.add_argument("--ring-passes", type=int, default=100,
-                    help="passes per captured graph launch in the timed region")
+                    help="passes per ring run in the timed region")
     ap.add_argument("--fit-streams", type=int, default=2,
                     help="streams the fit requests of the timed region alternate over")
     ap.add_argument("--time-every", type=int, default=8,
